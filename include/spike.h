@@ -1,0 +1,185 @@
+/*
+ * spike.h -- C ABI of the MI355X recursive SPIKE banded solver.
+ *
+ * Solves A X = F and A^T X = F for an n x n banded matrix A with kl
+ * subdiagonals and ku superdiagonals, given in LAPACK band storage, for any
+ * number of leaf partitions p >= 1 (powers of two or not).  The method is the
+ * recursive SPIKE algorithm of Spring, Polizzi and Sameh, "A Feature Complete
+ * SPIKE Banded Algorithm and Solver" (arXiv:1811.03559):
+ *
+ *   - A = D S: D holds the p diagonal blocks A_i, S the spikes
+ *     V_i = A_i^{-1} B_i and W_i = A_i^{-1} C_i (section "Central concept of
+ *     SPIKE", eqs. partitioning, BandChats, spikes);
+ *   - blocks 1..p-1 are factored LU and block p UL (section "Optimizing
+ *     per-partition costs"), non-pivoting with diagonal boosting or with
+ *     partial pivoting (section "An efficient pivoting scheme"; UL through the
+ *     reversal permutation Q of eq. Qmat);
+ *   - only spike tips are formed, with truncated sweeps (Table tab:sweeps);
+ *   - the reduced system is solved recursively, S^[l] = D^[l] S^[l+1]
+ *     (section "Recursive reduced system", eqs. RED_SYS_RECA/RED_SYS_RECB,
+ *     D1Inverse, S2Inverse), here over a merge tree valid for any p;
+ *   - the transpose solve reuses the same factorisation,
+ *     A^T = S^T D^T (section "Transpose solve option", eqs. gform1/gform2,
+ *     ATF, sweeps_in_D, transred1/transred2).
+ *
+ * All device pointers are allocated by the caller.  The library never
+ * allocates device memory: the factorisation lives in a caller-provided
+ * workspace whose size spike_workspace_size() reports.
+ *
+ * Calls that take a stream are asynchronous: they validate arguments on the
+ * host, enqueue kernels on the stream and return.  Numerical status (zero
+ * pivots, boosts, refinement) is written on the device and read with
+ * spike_info() after the stream has been synchronised.
+ *
+ * Return codes: 0 on success; -i when argument i is invalid (LAPACK style,
+ * 1-based position in the call); SPIKE_ERR_HIP - e (e = hipError_t) when a
+ * HIP runtime call or launch fails.
+ */
+#ifndef SPIKE_H
+#define SPIKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPIKE_ERR_HIP (-1000)
+
+#ifndef SPIKE_API
+#define SPIKE_API __attribute__((visibility("default")))
+#endif
+
+typedef struct spike_handle_s *spike_handle;
+
+/* Options.  spike_default_opts() fills the defaults given in brackets. */
+typedef struct spike_opts {
+    int32_t p;          /* leaf partitions; 0 = planner's choice          [0]    */
+    int32_t pivot;      /* 0 = non-pivoting LU/UL with diagonal boosting,
+                           1 = partial pivoting inside each block         [0]    */
+    int32_t precision;  /* 0 = FP64 throughout; 1 = FP32 block factors and
+                           sweeps, FP64 reduced system, FP64 residual and
+                           iterative refinement                           [0]    */
+    int32_t sizing;     /* 0 = equal partitions; 1 = first/last partitions
+                           enlarged by the ratio R13 of the paper's
+                           load-balancing section                        [0]    */
+    double K;           /* solve/factor cost constant K = K2/K1 used by
+                           R13 sizing; <= 0 selects 1.0                   [0]    */
+    int32_t nrhs_hint;  /* expected nrhs for R13 sizing; 0 = unknown       [0]    */
+    int32_t nrhs_max;   /* largest nrhs handled in one pass; larger solves
+                           are split into passes; sizes the workspace    [64]    */
+    double boost_tau;   /* non-pivoting only: a pivot with |u_jj| <
+                           boost_tau * ||A_i||_1 is boosted by that amount
+                           (sign kept); 0 disables boosting; < 0 selects
+                           sqrt(unit roundoff of the factor precision)  [-1]    */
+    int32_t max_refine; /* refinement iteration cap; < 0 selects 6 with
+                           precision 1 and 0 with precision 0.  With
+                           precision 0 a positive value refines solves of
+                           a factorisation whose pivots were boosted     [-1]    */
+    double refine_tol;  /* backward-error target of refinement        [1e-13]    */
+} spike_opts;
+
+/* Device-side status, read by spike_info() (blocking copy). */
+typedef struct spike_status {
+    int64_t info;       /* 0; i in [1, n]: first exactly-zero pivot at global
+                           row i (1-based), boosting off or pivoting;
+                           n + 1 + j: interface system j (0-based, between
+                           partitions j and j+1) is singular               */
+    int32_t n_boosts;   /* pivots boosted during the factorisation        */
+    int32_t refine_iters; /* refinement iterations of the last solve      */
+    double min_abs_pivot; /* smallest |u_jj| over all blocks              */
+    double berr;        /* backward error of the last refined solve, or -1 */
+} spike_status;
+
+/* Partition plan, as computed by the host planner (no device access). */
+typedef struct spike_plan_info {
+    int32_t p;          /* leaf partitions                                */
+    int32_t levels;     /* depth of the reduced-system merge tree         */
+    int32_t merges;     /* number of 2x2-block interface systems (= p-1)  */
+    int64_t reduced_size; /* unknowns of the reduced system, (kl+ku)(p-1) */
+    size_t workspace_bytes;
+} spike_plan_info;
+
+/* Fill *opts with the defaults above. */
+SPIKE_API void spike_default_opts(spike_opts *opts);
+
+/* Host-only planner query.  Writes the plan summary to *out and, when
+ * sizes is not NULL, the p partition sizes (int64) in order.  sizes must hold
+ * at least p entries when opts->p > 0, else 4096.  Touches no device.
+ * Errors: -1 n < 0, -2 kl < 0, -3 ku < 0, -4 bad opts (p < 0, p > n, or a
+ * partition smaller than kl+ku, or an unknown mode). */
+SPIKE_API int spike_plan_query(int64_t n, int32_t kl, int32_t ku, const spike_opts *opts,
+                     spike_plan_info *out, int64_t *sizes);
+
+/* Bytes of device workspace spike_factor() needs.  Same errors as
+ * spike_plan_query. */
+SPIKE_API int spike_workspace_size(int64_t n, int32_t kl, int32_t ku,
+                         const spike_opts *opts, size_t *bytes);
+
+/* Factor A (recursive SPIKE factorisation stage: block factors, spike tips,
+ * recursive reduced-system factors).
+ *   n, kl, ku   order and bandwidths (n >= 0, kl >= 0, ku >= 0)
+ *   dAB         device, read-only: LAPACK band storage, column-major,
+ *               A(i,j) at dAB[(ku + i - j) + j*ldab], ldab >= kl+ku+1.  With
+ *               precision 1 the refinement residual reads dAB, so it must stay
+ *               valid and unchanged until spike_destroy.
+ *   opts        NULL for defaults
+ *   dWork       device workspace of work_bytes >= spike_workspace_size(),
+ *               256-byte aligned, owned by the caller, holding the
+ *               factorisation until spike_destroy
+ *   stream      HIP stream all work is enqueued on
+ *   out         receives a host handle (host memory owned by the library)
+ * Errors: -1..-3 as above, -4 dAB NULL, -5 ldab too small, -6 bad opts,
+ * -7 dWork NULL or misaligned, -8 work_bytes too small, -10 out NULL. */
+SPIKE_API int spike_factor(int64_t n, int32_t kl, int32_t ku, const double *dAB,
+                 int64_t ldab, const spike_opts *opts, void *dWork,
+                 size_t work_bytes, hipStream_t stream, spike_handle *out);
+
+/* Solve A X = F in place: dB (device, column-major n x nrhs, ldb >= n) holds
+ * F on entry and X on exit.  Uses the handle's workspace; calls on one handle
+ * must be ordered (same stream or synchronised).  If the factorisation
+ * reported info != 0 the kernels leave dB untouched.
+ * Errors: -1 bad handle, -2 nrhs < 0, -3 dB NULL (with nrhs > 0), -4 ldb < n. */
+SPIKE_API int spike_solve(spike_handle h, int32_t nrhs, double *dB, int64_t ldb,
+                hipStream_t stream);
+
+/* Solve A^T X = F in place with the same factorisation (transpose S stage,
+ * transpose recursive reduced system, transpose D stage).  Arguments and
+ * errors as spike_solve. */
+SPIKE_API int spike_solve_transpose(spike_handle h, int32_t nrhs, double *dB,
+                          int64_t ldb, hipStream_t stream);
+
+/* Copy the device status to *out (blocking device-to-host copy; synchronise
+ * the factor/solve stream first).  Errors: -1 bad handle, -2 out NULL. */
+SPIKE_API int spike_info(spike_handle h, spike_status *out);
+
+/* Plan of an existing handle (host data, no device access). */
+SPIKE_API int spike_handle_plan(spike_handle h, spike_plan_info *out);
+
+/* Kernel timing (profiling aid).  spike_profile_enable(1) clears previous
+ * records and, until spike_profile_enable(0), brackets every kernel launch of
+ * the library with HIP events recorded on the launch stream.
+ * spike_profile_report() waits for the recorded events and writes, per
+ * kernel name, the number of launches and their summed duration (up to cap
+ * entries; *count receives the number of distinct kernels). */
+typedef struct spike_kernel_time {
+    char name[48];
+    int32_t calls;
+    double total_ms;
+} spike_kernel_time;
+
+SPIKE_API int spike_profile_enable(int on);
+SPIKE_API int spike_profile_report(spike_kernel_time *out, int cap, int *count);
+
+/* Release the host handle.  The caller may free dWork afterwards (after the
+ * stream work using it has completed). */
+SPIKE_API int spike_destroy(spike_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIKE_H */

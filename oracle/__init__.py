@@ -50,6 +50,8 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             lib.orc_gbsv.restype = _i64
             lib.orc_gbsv.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _int, _p, _i64]
+            lib.orc_gbsv_nt.restype = _i64
+            lib.orc_gbsv_nt.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _p, _p, _i64]
             lib.orc_gbtrf.restype = _i64
             lib.orc_gbtrf.argtypes = [_i64, _int, _int, _p, _i64, _int, _p, _p]
             lib.orc_gbmv.restype = None
@@ -94,6 +96,18 @@ def gbsv(ab, kl, ku, F, pivot=True, trans=False):
     if info != 0:
         raise ZeroDivisionError("oracle factorisation info=%d" % info)
     return X[0] if squeeze else X
+
+
+def gbsv_nt(ab, kl, ku, F, pivot=True):
+    """One factorisation, then (A^{-1} F, A^{-T} F)."""
+    ab, n, ldab = _band(ab, kl, ku)
+    X = _rhs(F, n)
+    Xt = X.copy()
+    info = _load().orc_gbsv_nt(n, kl, ku, ab.ctypes.data, ldab, int(bool(pivot)), X.shape[0],
+                               X.ctypes.data, Xt.ctypes.data, max(n, 1))
+    if info != 0:
+        raise ZeroDivisionError("oracle factorisation info=%d" % info)
+    return X, Xt
 
 
 def gbtrf(ab, kl, ku, pivot=True):

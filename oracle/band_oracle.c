@@ -208,6 +208,32 @@ ORC_EXPORT int64_t orc_gbsv(int64_t n, int kl, int ku, const double *ab,
     return info;
 }
 
+/* One factorisation, then A X = F on B and A^T X = F on Bt (both n x nrhs,
+ * leading dimension ldb).  Returns as orc_gbsv. */
+ORC_EXPORT int64_t orc_gbsv_nt(int64_t n, int kl, int ku, const double *ab,
+                               int64_t ldab, int pivot, int nrhs, double *B,
+                               double *Bt, int64_t ldb) {
+    if (n <= 0) return n < 0 ? -1 : 0;
+    work_band b;
+    if (make_work_band(&b, n, kl, ku, ab, ldab, pivot)) return -100;
+    int64_t *ipiv = NULL;
+    int64_t info;
+    if (pivot) {
+        ipiv = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+        info = lu_piv(&b, ipiv);
+    } else {
+        info = lu_nopiv(&b);
+    }
+    if (info == 0)
+        for (int c = 0; c < nrhs; ++c) {
+            solve_n(&b, ipiv, B + (int64_t)c * ldb);
+            solve_t(&b, ipiv, Bt + (int64_t)c * ldb);
+        }
+    free(ipiv);
+    free(b.w);
+    return info;
+}
+
 /* Factor only, returning the working band (ld = 2kl+ku+1 when pivoting,
  * kl+ku+1 otherwise, U superdiagonals first) and the pivots; used by tests
  * that check the pivot invariants and reconstruct P A = L U. */

@@ -1,0 +1,79 @@
+// Stage sequencing: dispatch on the panel widths and precision chosen by the
+// planner, and order the leaf and merge launches of each stage.
+#include "spike_launch.hpp"
+
+namespace spike {
+
+namespace {
+
+template <typename T>
+int leaf_factor(int nb, const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  switch (nb) {
+    case 32: return run_leaf_factor<32, T>(k, c, st);
+    case 16: return run_leaf_factor<16, T>(k, c, st);
+    default: return run_leaf_factor<8, T>(k, c, st);
+  }
+}
+
+template <typename T>
+int leaf_phase(int nb, const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
+               int phase) {
+  switch (nb) {
+    case 32: return run_leaf_phase<32, T>(k, c, st, B, ldb, nrhs, phase);
+    case 16: return run_leaf_phase<16, T>(k, c, st, B, ldb, nrhs, phase);
+    default: return run_leaf_phase<8, T>(k, c, st, B, ldb, nrhs, phase);
+  }
+}
+
+int merge_factor(int nbd, const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  switch (nbd) {
+    case 32: return run_merge_factor<32>(k, c, st);
+    case 16: return run_merge_factor<16>(k, c, st);
+    default: return run_merge_factor<8>(k, c, st);
+  }
+}
+
+int merge_solve(int nbd, const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, bool trans) {
+  switch (nbd) {
+    case 32: return run_merge_solve<32>(k, c, st, nrhs, trans);
+    case 16: return run_merge_solve<16>(k, c, st, nrhs, trans);
+    default: return run_merge_solve<8>(k, c, st, nrhs, trans);
+  }
+}
+
+}  // namespace
+
+int launch_init_status(DevStatus* s, hipStream_t st) { return run_init_status(s, st); }
+
+int launch_factor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  int e = c.fp32 ? leaf_factor<float>(c.nb, k, c, st) : leaf_factor<double>(c.nb, k, c, st);
+  if (e) return e;
+  if (k.p > 1) return merge_factor(c.nb_dense, k, c, st);
+  return 0;
+}
+
+int launch_solve(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
+                 bool trans) {
+  auto leaf = [&](int phase) {
+    return c.fp32 ? leaf_phase<float>(c.nb, k, c, st, B, ldb, nrhs, phase)
+                  : leaf_phase<double>(c.nb, k, c, st, B, ldb, nrhs, phase);
+  };
+  int e;
+  if (!trans) {
+    if ((e = leaf(0))) return e;            // D stage
+    if (k.p > 1) {
+      if ((e = merge_solve(c.nb_dense, k, c, st, nrhs, false))) return e;
+      if ((e = leaf(1))) return e;          // retrieval
+    }
+  } else {
+    if ((e = leaf(2))) return e;            // Z sweeps of the transpose S stage
+    if (k.p > 1) {
+      if ((e = run_gform(k, st, B, ldb, nrhs))) return e;
+      if ((e = merge_solve(c.nb_dense, k, c, st, nrhs, true))) return e;
+      if ((e = leaf(3))) return e;          // transpose D stage
+    }
+  }
+  return 0;
+}
+
+}  // namespace spike

@@ -1,0 +1,32 @@
+// One translation unit per group of kernel instantiations, selected by the
+// build with -DSPIKE_INST_LEAF (with SPIKE_NB, SPIKE_T), -DSPIKE_INST_MERGE
+// (with SPIKE_NB) or -DSPIKE_INST_COMMON, so the kernels compile in parallel.
+#include "spike_kernels.hpp"
+
+namespace spike {
+
+#if defined(SPIKE_INST_LEAF)
+template int run_leaf_factor<SPIKE_NB, SPIKE_T>(const KParams&, const LaunchCfg&, hipStream_t);
+template int run_leaf_phase<SPIKE_NB, SPIKE_T>(const KParams&, const LaunchCfg&, hipStream_t, double*, int64_t,
+                                                int, int);
+#elif defined(SPIKE_INST_MERGE)
+template int run_merge_factor<SPIKE_NB>(const KParams&, const LaunchCfg&, hipStream_t);
+template int run_merge_solve<SPIKE_NB>(const KParams&, const LaunchCfg&, hipStream_t, int, bool);
+#elif defined(SPIKE_INST_COMMON)
+int run_init_status(DevStatus* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, s);
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
+int run_gform(const KParams& k, hipStream_t st, const double* B, int64_t ldb, int nrhs) {
+  ProfScope ps("k_gform", st);
+  hipLaunchKernelGGL(k_gform, dim3(k.p - 1), dim3(NT), 0, st, k, B, ldb, nrhs);
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+#else
+#error "select an instantiation group"
+#endif
+
+}  // namespace spike

@@ -1,0 +1,80 @@
+// Kernel parameter block and host launch entry points (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "spike_types.hpp"
+
+#ifndef SPIKE_ERR_HIP
+#define SPIKE_ERR_HIP (-1000)
+#endif
+
+namespace spike {
+
+// Everything a kernel needs, passed by value.  Pointers are device pointers
+// into the caller's workspace (or the caller's band for dAB).
+struct KParams {
+  int64_t n;
+  int kl, ku, kw, kmax, p, pivot;
+  int64_t ldw;
+  int side_ld;
+  int R;                 // columns per solve pass (workspace sizing)
+  int64_t sscr_ld;       // rows of each leaf's solve scratch
+  double boost_tau;      // relative boosting threshold (<= 0: off)
+  const double* dAB;
+  int64_t ldab;
+  DevStatus* status;
+  const LeafDesc* leaves;
+  const MergeDesc* merges;
+  const int* cptr;
+  const Contrib* contrib;
+  void* band;            // block factors (T)
+  void* lpan;            // dense L panel tiles of pivoting factors (T)
+  int64_t lpld;          // leading dimension of an L panel tile (nb + max(kl, ku))
+  int* ipiv;
+  double* bhat;
+  double* chat;
+  void* side;            // truncation side blocks (T)
+  double* tips;
+  double* sfac;
+  int* spiv;
+  double* coef;
+  double* qw;
+  void* fscr;            // factor-stage spike scratch (T)
+  double* nodeval;
+  double* st;
+  double* xint;
+  double* ztip;
+  double* crl;
+  double* sscr;
+  const int32_t* skip;   // when non-null and *skip != 0 the solve kernels idle
+};
+
+struct LaunchCfg {
+  int nb, nb_dense;
+  bool fp32;
+  size_t leaf_lds, merge_lds;
+  std::vector<int> level_off;
+};
+
+// Runners, instantiated per panel width / precision in spike_inst.hip.
+template <int NB, typename T>
+int run_leaf_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);
+template <int NB, typename T>
+int run_leaf_phase(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
+                   int phase);
+template <int NBD>
+int run_merge_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);
+template <int NBD>
+int run_merge_solve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, bool trans);
+int run_init_status(DevStatus* s, hipStream_t st);
+int run_gform(const KParams& k, hipStream_t st, const double* B, int64_t ldb, int nrhs);
+
+int launch_init_status(DevStatus* s, hipStream_t st);
+int launch_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);
+int launch_solve(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
+                 bool trans);
+
+}  // namespace spike

@@ -1,0 +1,245 @@
+"""ctypes binding of ``libspike.so`` (the C ABI in ``include/spike.h``).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+PyTorch provides device memory and the current stream.  If the library is
+missing, every call raises: there is no fallback path.
+
+Layouts: a band is a float64 tensor of shape ``(n, ldab)`` (C order), i.e.
+LAPACK column-major band storage with ``ab[j, ku + i - j] = A(i, j)``.  A
+right-hand-side block is a float64 tensor of shape ``(nrhs, n)`` (C order),
+i.e. column-major ``n x nrhs`` with ``ldb = n``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspike.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "spike.h")
+
+_c_i32 = ctypes.c_int32
+_c_i64 = ctypes.c_int64
+_c_dbl = ctypes.c_double
+_c_size = ctypes.c_size_t
+_c_p = ctypes.c_void_p
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("p", _c_i32), ("pivot", _c_i32), ("precision", _c_i32), ("sizing", _c_i32),
+                ("K", _c_dbl), ("nrhs_hint", _c_i32), ("nrhs_max", _c_i32),
+                ("boost_tau", _c_dbl), ("max_refine", _c_i32), ("refine_tol", _c_dbl)]
+
+
+class Status(ctypes.Structure):
+    _fields_ = [("info", _c_i64), ("n_boosts", _c_i32), ("refine_iters", _c_i32),
+                ("min_abs_pivot", _c_dbl), ("berr", _c_dbl)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("p", _c_i32), ("levels", _c_i32), ("merges", _c_i32),
+                ("reduced_size", _c_i64), ("workspace_bytes", _c_size)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("calls", _c_i32), ("total_ms", _c_dbl)]
+
+
+class SpikeError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__("%s returned %d" % (fn, code))
+        self.code = code
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Load libspike.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libspike.so not built; run paper_1811_03559_amd.build.build()")
+            L = ctypes.CDLL(LIB_PATH)
+            L.spike_default_opts.restype = None
+            L.spike_default_opts.argtypes = [ctypes.POINTER(Opts)]
+            L.spike_plan_query.restype = ctypes.c_int
+            L.spike_plan_query.argtypes = [_c_i64, _c_i32, _c_i32, ctypes.POINTER(Opts),
+                                           ctypes.POINTER(PlanInfo), ctypes.POINTER(_c_i64)]
+            L.spike_workspace_size.restype = ctypes.c_int
+            L.spike_workspace_size.argtypes = [_c_i64, _c_i32, _c_i32, ctypes.POINTER(Opts),
+                                               ctypes.POINTER(_c_size)]
+            L.spike_factor.restype = ctypes.c_int
+            L.spike_factor.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, ctypes.POINTER(Opts),
+                                       _c_p, _c_size, _c_p, ctypes.POINTER(_c_p)]
+            L.spike_solve.restype = ctypes.c_int
+            L.spike_solve.argtypes = [_c_p, _c_i32, _c_p, _c_i64, _c_p]
+            L.spike_solve_transpose.restype = ctypes.c_int
+            L.spike_solve_transpose.argtypes = [_c_p, _c_i32, _c_p, _c_i64, _c_p]
+            L.spike_info.restype = ctypes.c_int
+            L.spike_info.argtypes = [_c_p, ctypes.POINTER(Status)]
+            L.spike_handle_plan.restype = ctypes.c_int
+            L.spike_handle_plan.argtypes = [_c_p, ctypes.POINTER(PlanInfo)]
+            L.spike_destroy.restype = ctypes.c_int
+            L.spike_destroy.argtypes = [_c_p]
+            L.spike_profile_enable.restype = ctypes.c_int
+            L.spike_profile_enable.argtypes = [ctypes.c_int]
+            L.spike_profile_report.restype = ctypes.c_int
+            L.spike_profile_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_int)]
+            _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Names the public header declares with SPIKE_API."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"SPIKE_API\s+[\w\s\*]+?\b(spike_\w+)\s*\(", txt)))
+
+
+def profile_enable(on=True):
+    """Start (clearing earlier records) or stop per-kernel HIP-event timing."""
+    rc = lib().spike_profile_enable(1 if on else 0)
+    if rc != 0:
+        raise SpikeError("spike_profile_enable", rc)
+
+
+def profile_report():
+    """{kernel name: (launches, summed milliseconds)} of the recorded launches."""
+    cap = 64
+    buf = (KernelTime * cap)()
+    cnt = ctypes.c_int()
+    rc = lib().spike_profile_report(buf, cap, ctypes.byref(cnt))
+    if rc != 0:
+        raise SpikeError("spike_profile_report", rc)
+    return {buf[i].name.decode(): (buf[i].calls, buf[i].total_ms) for i in range(min(cnt.value, cap))}
+
+
+def make_opts(p=0, pivot=False, precision="fp64", sizing="equal", K=0.0, nrhs_hint=0,
+              nrhs_max=64, boost_tau=-1.0, max_refine=-1, refine_tol=1e-13) -> Opts:
+    o = Opts()
+    lib().spike_default_opts(ctypes.byref(o))
+    o.p = int(p)
+    o.pivot = 1 if pivot else 0
+    o.precision = {"fp64": 0, "mixed": 1, 0: 0, 1: 1}[precision]
+    o.sizing = {"equal": 0, "r13": 1, 0: 0, 1: 1}[sizing]
+    o.K = float(K)
+    o.nrhs_hint = int(nrhs_hint)
+    o.nrhs_max = int(nrhs_max)
+    o.boost_tau = float(boost_tau)
+    o.max_refine = int(max_refine)
+    o.refine_tol = float(refine_tol)
+    return o
+
+
+def plan_query(n, kl, ku, **opts):
+    """Host-only planner query: dict with p, levels, merges, reduced_size,
+    workspace_bytes and the partition sizes."""
+    o = make_opts(**opts)
+    info = PlanInfo()
+    cap = max(int(opts.get("p", 0) or 0), 4096)
+    sizes = (_c_i64 * cap)()
+    rc = lib().spike_plan_query(int(n), int(kl), int(ku), ctypes.byref(o), ctypes.byref(info), sizes)
+    if rc != 0:
+        raise SpikeError("spike_plan_query", rc)
+    return {"p": info.p, "levels": info.levels, "merges": info.merges,
+            "reduced_size": info.reduced_size, "workspace_bytes": info.workspace_bytes,
+            "sizes": [sizes[i] for i in range(info.p)]}
+
+
+def workspace_size(n, kl, ku, **opts) -> int:
+    o = make_opts(**opts)
+    out = _c_size()
+    rc = lib().spike_workspace_size(int(n), int(kl), int(ku), ctypes.byref(o), ctypes.byref(out))
+    if rc != 0:
+        raise SpikeError("spike_workspace_size", rc)
+    return out.value
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Factorization:
+    """A SPIKE factorisation resident in a device workspace.
+
+    ``ab``: float64 CUDA tensor (n, ldab), LAPACK band storage.  The tensor is
+    kept referenced (mixed precision reads it for residuals)."""
+
+    def __init__(self, ab, kl, ku, *, stream=None, workspace=None, **opts):
+        import torch
+        if ab.dtype != torch.float64 or not ab.is_cuda or not ab.is_contiguous():
+            raise ValueError("band must be a contiguous float64 CUDA tensor")
+        self.n, self.ldab = int(ab.shape[0]), int(ab.shape[1])
+        self.kl, self.ku = int(kl), int(ku)
+        self.opts = make_opts(**opts)
+        self.nrhs_max = self.opts.nrhs_max
+        need = workspace_size(self.n, kl, ku, **opts)
+        if workspace is None:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=ab.device)
+        if workspace.numel() < need:
+            raise ValueError("workspace too small")
+        self.ab = ab
+        self.ws = workspace
+        self.device = ab.device
+        h = ctypes.c_void_p()
+        rc = lib().spike_factor(self.n, self.kl, self.ku, ctypes.c_void_p(ab.data_ptr()), self.ldab,
+                                ctypes.byref(self.opts), ctypes.c_void_p(workspace.data_ptr()),
+                                workspace.numel(), _stream_handle(stream), ctypes.byref(h))
+        if rc != 0:
+            raise SpikeError("spike_factor", rc)
+        self.h = h
+
+    def solve_(self, B, *, trans=False, stream=None):
+        """In-place solve on B ((nrhs, n) float64 CUDA tensor, C order)."""
+        import torch
+        if B.dtype != torch.float64 or not B.is_cuda:
+            raise ValueError("B must be a float64 CUDA tensor")
+        if B.dim() == 1:
+            B = B.view(1, -1)
+        if B.shape[1] != self.n or B.stride(1) != 1:
+            raise ValueError("B must have shape (nrhs, n) with unit column stride")
+        ldb = B.stride(0) if B.shape[0] > 1 else max(self.n, 1)
+        fn = lib().spike_solve_transpose if trans else lib().spike_solve
+        rc = fn(self.h, int(B.shape[0]), ctypes.c_void_p(B.data_ptr()), int(ldb), _stream_handle(stream))
+        if rc != 0:
+            raise SpikeError("spike_solve_transpose" if trans else "spike_solve", rc)
+        return B
+
+    def info(self):
+        st = Status()
+        rc = lib().spike_info(self.h, ctypes.byref(st))
+        if rc != 0:
+            raise SpikeError("spike_info", rc)
+        return {"info": st.info, "n_boosts": st.n_boosts, "refine_iters": st.refine_iters,
+                "min_abs_pivot": st.min_abs_pivot, "berr": st.berr}
+
+    def plan(self):
+        info = PlanInfo()
+        rc = lib().spike_handle_plan(self.h, ctypes.byref(info))
+        if rc != 0:
+            raise SpikeError("spike_handle_plan", rc)
+        return {"p": info.p, "levels": info.levels, "merges": info.merges,
+                "reduced_size": info.reduced_size, "workspace_bytes": info.workspace_bytes}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().spike_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def levels_for(p: int) -> int:
+    return 0 if p <= 1 else math.ceil(math.log2(p))

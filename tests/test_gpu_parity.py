@@ -1,0 +1,160 @@
+"""GPU parity: the HIP recursive SPIKE solver (through the C ABI) against the
+FP64 oracle on the same seeded inputs.  Bars: relative residual <= 1e-13 and
+forward error <= 1e-11 * kappa_1 (kappa from the oracle's estimate), for
+non-transpose and transpose solves, with and without partial pivoting, for
+power-of-two and other partition counts, ragged partitions and several
+bandwidths including unequal ones."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import check, run
+from paper_1811_03559_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dd_band(n, kl, ku, seed, mult=1.0, add=1.0):
+    return inputs.band_dominant(n, kl, ku, inputs.rng_for(seed), diag_mult=mult, diag_add=add)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("pivot", [False, True])
+def test_cfg0(p, trans, pivot):
+    """n=4096, kl=ku=4, nrhs=1, diagonal = row abs-sum + 1 (p=3 is the
+    non-power-of-two case); manufactured solution F = A X_true."""
+    ab, kl, ku, X_true = inputs.cfg0()
+    F = oracle.gbmv(ab, kl, ku, X_true, trans=trans)
+    X, info, plan = run(ab, kl, ku, F, trans=trans, p=p, pivot=pivot)
+    assert info["info"] == 0
+    assert plan["reduced_size"] == 8 * (p - 1)
+    check(ab, kl, ku, F, X, trans=trans, pivot=pivot, X_true=X_true)
+
+
+GRID_P = [1, 2, 3, 4, 5, 7, 8, 13]
+GRID_K = [(1, 1), (2, 5), (5, 2), (4, 4), (0, 3), (3, 0)]
+
+
+@pytest.mark.parametrize("p", GRID_P)
+@pytest.mark.parametrize("kl,ku", GRID_K)
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("pivot", [False, True])
+def test_grid(p, kl, ku, trans, pivot):
+    n = 37 * p + 11
+    ab = dd_band(n, kl, ku, 7000 + 97 * p + 13 * kl + ku)
+    F = inputs.rhs(n, 3, inputs.rng_for(11 + p))
+    X, info, _ = run(ab, kl, ku, F, trans=trans, p=p, pivot=pivot)
+    assert info["info"] == 0
+    check(ab, kl, ku, F, X, trans=trans, pivot=pivot)
+
+
+@pytest.mark.parametrize("k", [32, 64, 160])
+@pytest.mark.parametrize("p", [2, 5, 8])
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("pivot", [False, True])
+def test_wide_band(k, p, trans, pivot):
+    n = p * (2 * k + 37) + 3
+    ab = dd_band(n, k, k, 9000 + k + p, mult=1.05, add=0.0)
+    F = inputs.rhs(n, 5, inputs.rng_for(k * p))
+    X, info, _ = run(ab, k, k, F, trans=trans, p=p, pivot=pivot)
+    assert info["info"] == 0
+    check(ab, k, k, F, X, trans=trans, pivot=pivot)
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_unequal_wide_band(trans):
+    n, kl, ku, p = 1500, 40, 17, 6
+    ab = dd_band(n, kl, ku, 31337)
+    F = inputs.rhs(n, 2, inputs.rng_for(2))
+    for pivot in (False, True):
+        X, info, _ = run(ab, kl, ku, F, trans=trans, p=p, pivot=pivot)
+        check(ab, kl, ku, F, X, trans=trans, pivot=pivot)
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_nrhs_split_into_passes(trans):
+    n, k, p = 900, 6, 5
+    ab = dd_band(n, k, k, 4)
+    F = inputs.rhs(n, 10, inputs.rng_for(4))
+    X, _, _ = run(ab, k, k, F, trans=trans, p=p, nrhs_max=4)
+    check(ab, k, k, F, X, trans=trans)
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_r13_sizing(trans):
+    n, k, p = 6000, 8, 9
+    ab = dd_band(n, k, k, 99)
+    F = inputs.rhs(n, 2, inputs.rng_for(99))
+    X, _, _ = run(ab, k, k, F, trans=trans, p=p, sizing="r13", K=4.0 / 3.0, nrhs_hint=2)
+    check(ab, k, k, F, X, trans=trans)
+
+
+@pytest.mark.parametrize("p", [2, 3, 8])
+@pytest.mark.parametrize("trans", [False, True])
+def test_pivoting_ill_conditioned(p, trans):
+    """N(0,1) band with row scales 10^U[-4,4] (no dominance): pivoting SPIKE
+    against the oracle's partial-pivoting solve."""
+    n, k = 3000, 8
+    ab = inputs.band_gaussian_rowscaled(n, k, k, inputs.rng_for(inputs.seed_for(2, p)))
+    X_true = inputs.rhs(n, 4, inputs.rng_for(5))
+    F = oracle.gbmv(ab, k, k, X_true, trans=trans)
+    X, info, _ = run(ab, k, k, F, trans=trans, p=p, pivot=True)
+    assert info["info"] == 0
+    Xo = oracle.gbsv(ab, k, k, F, pivot=True, trans=trans)
+    rr = oracle.relres(ab, k, k, X, F, trans=trans)
+    rr_o = oracle.relres(ab, k, k, Xo, F, trans=trans)
+    assert rr <= max(1e-13, 1e3 * rr_o), (rr, rr_o)
+
+
+def test_zero_pivot_boosting_and_pivoting():
+    """An exactly-zero leading pivot inside a partition: non-pivoting without
+    boosting reports it, with boosting counts a boost, pivoting solves it."""
+    n, k, p = 400, 3, 4
+    ab = dd_band(n, k, k, 5)
+    s = 100                       # first row of partition 1 (sizes 100 each)
+    ab[s, k] = 0.0                # A(s, s) = 0
+    F = inputs.rhs(n, 1, inputs.rng_for(6))
+    _, info, _ = run(ab, k, k, F, p=p, pivot=False, boost_tau=0.0)
+    assert info["info"] == s + 1
+    X, info, _ = run(ab, k, k, F, p=p, pivot=False, max_refine=10)
+    assert info["n_boosts"] >= 1 and info["info"] == 0
+    check(ab, k, k, F, X, pivot=True)
+    X, info, _ = run(ab, k, k, F, p=p, pivot=True)
+    assert info["info"] == 0 and info["n_boosts"] == 0
+    check(ab, k, k, F, X, pivot=True)
+
+
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("pivot", [False, True])
+def test_mixed_precision_refinement(trans, pivot):
+    """FP32 block factors and sweeps, FP64 reduced system, FP64 refinement to
+    a backward error <= 1e-13 (diagonal = row abs-sum * U[1.01, 1.5])."""
+    n, k, p = 20000, 16, 8
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(inputs.seed_for(3)), diag_mult_range=(1.01, 1.5))
+    X_true = inputs.rhs(n, 3, inputs.rng_for(3))
+    F = oracle.gbmv(ab, k, k, X_true, trans=trans)
+    X, info, _ = run(ab, k, k, F, trans=trans, p=p, pivot=pivot, precision="mixed")
+    assert 1 <= info["refine_iters"] <= 6, info
+    assert 0 <= info["berr"] <= 1e-13, info
+    check(ab, k, k, F, X, trans=trans, pivot=pivot, X_true=X_true)
+
+
+def test_repeat_solve_is_bitwise_deterministic():
+    import torch
+    from paper_1811_03559_amd import spike
+    n, k, p = 5000, 12, 7
+    ab = dd_band(n, k, k, 17)
+    F = inputs.rhs(n, 3, inputs.rng_for(17))
+    dab = torch.from_numpy(ab).cuda()
+    fac = spike.Factorization(dab, k, k, p=p)
+    outs = []
+    for _ in range(3):
+        B = torch.from_numpy(F.copy()).cuda()
+        fac.solve_(B)
+        outs.append(B.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    fac2 = spike.Factorization(dab, k, k, p=p)
+    B = torch.from_numpy(F.copy()).cuda()
+    fac2.solve_(B)
+    assert np.array_equal(outs[0], B.cpu().numpy())

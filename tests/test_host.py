@@ -1,0 +1,77 @@
+"""Host-side checks that need no GPU: the C ABI library loads and exports
+every symbol its header declares, and the planner's partition sizes, merge
+tree and reduced-system shape match the paper's closed forms."""
+import math
+
+import pytest
+
+import oracle
+from paper_1811_03559_amd import spike
+
+
+def test_library_exports_every_header_symbol():
+    names = spike.header_symbols()
+    assert {"spike_factor", "spike_solve", "spike_solve_transpose", "spike_workspace_size",
+            "spike_info", "spike_destroy"} <= set(names)
+    L = spike.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 7, 8, 13, 250, 256, 500])
+def test_plan_tree_shape(p):
+    kl = ku = 4
+    info = spike.plan_query(100_000, kl, ku, p=p)
+    assert info["p"] == p
+    assert info["merges"] == p - 1                         # p-1 interface solves
+    assert info["levels"] == (0 if p == 1 else math.ceil(math.log2(p)))
+    assert info["reduced_size"] == (kl + ku) * (p - 1)     # 2k(p-1) unknowns
+    assert sum(info["sizes"]) == 100_000
+
+
+def test_cfg0_equal_sizes():
+    info = spike.plan_query(4096, 4, 4, p=3)
+    assert info["sizes"] == [1365, 1365, 1366]
+    assert info["reduced_size"] == 16
+
+
+@pytest.mark.parametrize("nrhs,K", [(1, 1.0), (80, 4.0 / 3.0), (160, 4.0 / 3.0), (320, 2.0)])
+def test_r13_sizing_matches_closed_form(nrhs, K):
+    n, k, p = 1_000_000, 160, 16
+    info = spike.plan_query(n, k, k, p=p, sizing="r13", K=K, nrhs_hint=nrhs)
+    R13 = oracle.r13(K, nrhs / k)
+    n1 = n * R13 / (2 * R13 + p - 2)
+    n3 = n / (2 * R13 + p - 2)
+    sz = info["sizes"]
+    assert sum(sz) == n
+    assert sz[0] == sz[-1] == math.floor(n1)
+    assert all(abs(s - n3) <= 1 + p for s in sz[1:-1])
+    assert sz[0] / sz[1] == pytest.approx(R13, rel=1e-3)
+
+
+def test_argument_errors():
+    with pytest.raises(spike.SpikeError) as e:
+        spike.plan_query(-1, 2, 2)
+    assert e.value.code == -1
+    with pytest.raises(spike.SpikeError) as e:
+        spike.plan_query(100, -1, 2)
+    assert e.value.code == -2
+    with pytest.raises(spike.SpikeError) as e:
+        spike.plan_query(100, 2, -3)
+    assert e.value.code == -3
+    # infeasible p: partitions smaller than kl + ku
+    with pytest.raises(spike.SpikeError) as e:
+        spike.plan_query(100, 30, 30, p=5)
+    assert e.value.code == -4
+    with pytest.raises(spike.SpikeError) as e:
+        spike.plan_query(10, 1, 1, p=11)
+    assert e.value.code == -4
+
+
+def test_workspace_grows_with_problem():
+    a = spike.workspace_size(10_000, 4, 4, p=4)
+    b = spike.workspace_size(20_000, 4, 4, p=4)
+    c = spike.workspace_size(20_000, 8, 8, p=4)
+    d = spike.workspace_size(20_000, 8, 8, p=4, pivot=True)
+    assert a < b < c < d
+    assert spike.workspace_size(0, 3, 3) > 0
