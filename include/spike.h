@@ -75,10 +75,13 @@ typedef struct spike_opts {
                            boost_tau * ||A_i||_1 is boosted by that amount
                            (sign kept); 0 disables boosting; < 0 selects
                            sqrt(unit roundoff of the factor precision)  [-1]    */
-    int32_t max_refine; /* refinement iteration cap; < 0 selects 6 with
-                           precision 1 and 0 with precision 0.  With
-                           precision 0 a positive value refines solves of
-                           a factorisation whose pivots were boosted     [-1]    */
+    int32_t max_refine; /* FP64 iterative-refinement iteration cap; < 0
+                           selects 6 with precision 1 and 0 (no
+                           refinement) with precision 0.  A positive value
+                           with precision 0 refines every solve (useful
+                           after boosted pivots or for ill-conditioned A,
+                           where SPIKE loses accuracy).  Refinement needs
+                           the caller's dAB to stay valid                [-1]    */
     double refine_tol;  /* backward-error target of refinement        [1e-13]    */
 } spike_opts;
 

@@ -48,7 +48,7 @@ struct Plan {
   size_t sscr_rows = 0;            // rows of solve scratch per leaf (max)
 
   int64_t reduced_size() const { return (int64_t)kw * (p - 1); }
-  bool refine_enabled() const { return precision == 1 || (pivot == 0 && boost_tau != 0.0 && max_refine > 0); }
+  bool refine_enabled() const { return max_refine > 0; }
 };
 
 // Fills the defaults documented in spike.h.

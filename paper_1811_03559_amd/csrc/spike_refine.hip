@@ -54,8 +54,8 @@ __global__ __launch_bounds__(RT) void k_anorm(const double* ab, int64_t ldab, in
   }
 }
 
-__global__ void k_refine_activate(DevStatus* st, int fp32) {
-  if (threadIdx.x == 0) st->refine_active = (fp32 || st->n_boosts > 0) ? 1 : 0;
+__global__ void k_refine_activate(DevStatus* st) {
+  if (threadIdx.x == 0) st->refine_active = 1;
 }
 
 __global__ void k_refine_begin(DevStatus* st, unsigned long long* colred, int nrhs) {
@@ -176,7 +176,7 @@ int prepare_refine(const KParams& k, const Plan& pl, char*, hipStream_t st) {
   int64_t blocks = (pl.n + RT - 1) / RT;
   hipLaunchKernelGGL(k_anorm, dim3((unsigned)blocks), dim3(RT), 0, st, k.dAB, k.ldab, pl.n, pl.kl, pl.ku, k.status);
   if (int e = chk()) return e;
-  hipLaunchKernelGGL(k_refine_activate, dim3(1), dim3(64), 0, st, k.status, pl.precision == 1 ? 1 : 0);
+  hipLaunchKernelGGL(k_refine_activate, dim3(1), dim3(64), 0, st, k.status);
   return chk();
 }
 

@@ -90,21 +90,46 @@ def test_r13_sizing(trans):
     check(ab, k, k, F, X, trans=trans)
 
 
+# (n, kl, ku, p, diagonal multiplier): condition numbers 6e2..2e5, from 7 to
+# 2819 row exchanges in the oracle's elimination
+SWAP_CASES = [(400, 3, 3, 4, 0.3), (500, 5, 2, 5, 0.5), (600, 8, 8, 3, 0.3), (800, 2, 5, 7, 0.5),
+              (2000, 40, 17, 6, 0.2), (3000, 64, 64, 5, 0.02), (2000, 32, 32, 4, 0.05)]
+
+
+@pytest.mark.parametrize("n,kl,ku,p,mult", SWAP_CASES)
+@pytest.mark.parametrize("trans", [False, True])
+def test_pivoting_with_row_swaps(n, kl, ku, p, mult, trans):
+    """Not diagonally dominant (diagonal = mult * row abs-sum, mult < 1), so
+    partial pivoting exchanges many rows inside every panel."""
+    ab = inputs.band_dominant(n, kl, ku, inputs.rng_for(n + kl), diag_mult=mult)
+    _, _, ipiv = oracle.gbtrf(ab, kl, ku, pivot=True)
+    assert np.count_nonzero(ipiv != np.arange(n)) > 0
+    X_true = inputs.rhs(n, 3, inputs.rng_for(n))
+    F = oracle.gbmv(ab, kl, ku, X_true, trans=trans)
+    X, info, _ = run(ab, kl, ku, F, trans=trans, p=p, pivot=True)
+    assert info["info"] == 0
+    check(ab, kl, ku, F, X, trans=trans, pivot=True, X_true=X_true)
+
+
 @pytest.mark.parametrize("p", [2, 3, 8])
 @pytest.mark.parametrize("trans", [False, True])
 def test_pivoting_ill_conditioned(p, trans):
-    """N(0,1) band with row scales 10^U[-4,4] (no dominance): pivoting SPIKE
-    against the oracle's partial-pivoting solve."""
+    """N(0,1) band with row scales 10^U[-4,4] (no dominance, condition 1e11 to
+    1e13).  Pivoting SPIKE loses accuracy at such condition numbers (the
+    paper reports it beyond 1e8, growing with the partition count), so the
+    unrefined residual is only bounded loosely; three FP64 refinement steps
+    with the same factors must reach the 1e-13 bar."""
     n, k = 3000, 8
     ab = inputs.band_gaussian_rowscaled(n, k, k, inputs.rng_for(inputs.seed_for(2, p)))
     X_true = inputs.rhs(n, 4, inputs.rng_for(5))
     F = oracle.gbmv(ab, k, k, X_true, trans=trans)
     X, info, _ = run(ab, k, k, F, trans=trans, p=p, pivot=True)
     assert info["info"] == 0
-    Xo = oracle.gbsv(ab, k, k, F, pivot=True, trans=trans)
     rr = oracle.relres(ab, k, k, X, F, trans=trans)
-    rr_o = oracle.relres(ab, k, k, Xo, F, trans=trans)
-    assert rr <= max(1e-13, 1e3 * rr_o), (rr, rr_o)
+    assert rr <= 1e-9, rr
+    X, info, _ = run(ab, k, k, F, trans=trans, p=p, pivot=True, max_refine=3)
+    rr_ref = oracle.relres(ab, k, k, X, F, trans=trans)
+    assert rr_ref <= 1e-13 and info["berr"] <= 1e-13, (rr, rr_ref, info)
 
 
 def test_zero_pivot_boosting_and_pivoting():
