@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libspike.so")
 OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPIKE_OFFLOAD_ARCH", "gfx950")
 NBS = (8, 16, 32)
+HTS = (1, 2, 4, 8, 10, 16)
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fvisibility=hidden",
@@ -43,6 +44,10 @@ def units() -> list[tuple[str, str, list[str]]]:
                       ["-DSPIKE_INST_LEAF", f"-DSPIKE_T={t}", f"-DSPIKE_NB={nb}"]))
     for nb in NBS:
         u.append((f"merge_{nb}.o", "spike_inst.hip", ["-DSPIKE_INST_MERGE", f"-DSPIKE_NB={nb}"]))
+    for t in ("double", "float"):
+        for ht in HTS:
+            u.append((f"fast_{t}_{ht}.o", "spike_inst.hip",
+                      ["-DSPIKE_INST_FAST", f"-DSPIKE_T={t}", f"-DSPIKE_HT={ht}"]))
     u.append(("common.o", "spike_inst.hip", ["-DSPIKE_INST_COMMON"]))
     for src in ("spike_dispatch.hip", "spike_refine.hip", "spike_plan.cpp", "spike_api.cpp",
                 "spike_profile.cpp"):

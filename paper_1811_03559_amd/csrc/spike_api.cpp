@@ -88,6 +88,8 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   k.ztip = at<double>(w, pl.off_ztip);
   k.crl = at<double>(w, pl.off_crl);
   k.sscr = at<double>(w, pl.off_sscr);
+  k.fast_tips = (pl.fast && pl.p >= 3) ? 1 : 0;
+  k.dinv = w + pl.off_dinv;
 
   spike::LaunchCfg& c = h->cfg;
   c.nb = pl.nb;
@@ -96,6 +98,16 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   c.leaf_lds = pl.leaf_lds;
   c.merge_lds = pl.merge_lds;
   c.level_off = pl.level_off;
+  c.fast = pl.fast;
+  c.ht = pl.ht;
+  c.fast_lds = pl.fast_lds;
+  c.fast_min_nrhs = 2;
+  {
+    int maxm = 0;
+    for (auto& L : pl.leaves) maxm = L.m > maxm ? L.m : maxm;
+    c.dinv_chunks = ((maxm + 15) / 16 * 32 + 255) / 256;
+    if (c.dinv_chunks < 1) c.dinv_chunks = 1;
+  }
 }
 
 int upload(spike_handle h, hipStream_t st) {

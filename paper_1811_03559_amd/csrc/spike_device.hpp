@@ -369,12 +369,16 @@ __device__ void wg_utsweep(const Acc& A, const Mat<V>& X, int ncol, int row_min,
   for (int J = (max(row_min, 0) / NB) * NB; J < m; J += NB) {
     const int jb = min(NB, m - J);
     const int r0 = max(row_min, J - kuw);
-    const int nrows = J + jb - r0;
     const int base = J - kuw;
+    // Rows [J, row_min) of the first panel hold zeros in P: the substitution
+    // below multiplies them by the zero right-hand side, and stale LDS there
+    // could be a NaN pattern.
+    const int lrow = min(r0, J);
+    const int nrows = J + jb - lrow;
     for (int idx = tid; idx < nrows * jb; idx += NT) {
       int rr = idx % nrows, c = idx / nrows;
-      int i = r0 + rr, col = J + c;
-      P[(i - base) + c * ldP] = (i <= col && A.in(i, col)) ? A.at(i, col) : T(0);
+      int i = lrow + rr, col = J + c;
+      P[(i - base) + c * ldP] = (i >= row_min && i <= col && A.in(i, col)) ? A.at(i, col) : T(0);
     }
     __syncthreads();
     const int lo = max(J, row_min);

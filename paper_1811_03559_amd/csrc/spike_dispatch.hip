@@ -25,6 +25,30 @@ int leaf_phase(int nb, const KParams& k, const LaunchCfg& c, hipStream_t st, dou
   }
 }
 
+template <typename T>
+int fast_factor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  switch (c.ht) {
+    case 1: return run_fast_factor<T, 1>(k, c, st);
+    case 2: return run_fast_factor<T, 2>(k, c, st);
+    case 4: return run_fast_factor<T, 4>(k, c, st);
+    case 8: return run_fast_factor<T, 8>(k, c, st);
+    case 10: return run_fast_factor<T, 10>(k, c, st);
+    default: return run_fast_factor<T, 16>(k, c, st);
+  }
+}
+
+template <typename T>
+int fast_phase(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs, int phase) {
+  switch (c.ht) {
+    case 1: return run_fast_phase<T, 1>(k, c, st, B, ldb, nrhs, phase);
+    case 2: return run_fast_phase<T, 2>(k, c, st, B, ldb, nrhs, phase);
+    case 4: return run_fast_phase<T, 4>(k, c, st, B, ldb, nrhs, phase);
+    case 8: return run_fast_phase<T, 8>(k, c, st, B, ldb, nrhs, phase);
+    case 10: return run_fast_phase<T, 10>(k, c, st, B, ldb, nrhs, phase);
+    default: return run_fast_phase<T, 16>(k, c, st, B, ldb, nrhs, phase);
+  }
+}
+
 int merge_factor(int nbd, const KParams& k, const LaunchCfg& c, hipStream_t st) {
   switch (nbd) {
     case 32: return run_merge_factor<32>(k, c, st);
@@ -48,13 +72,21 @@ int launch_init_status(DevStatus* s, hipStream_t st) { return run_init_status(s,
 int launch_factor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
   int e = c.fp32 ? leaf_factor<float>(c.nb, k, c, st) : leaf_factor<double>(c.nb, k, c, st);
   if (e) return e;
+  if (c.fast) {
+    e = c.fp32 ? fast_factor<float>(k, c, st) : fast_factor<double>(k, c, st);
+    if (e) return e;
+  }
   if (k.p > 1) return merge_factor(c.nb_dense, k, c, st);
   return 0;
 }
 
 int launch_solve(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
                  bool trans) {
+  const bool use_fast = c.fast && nrhs >= c.fast_min_nrhs;
   auto leaf = [&](int phase) {
+    if (use_fast)
+      return c.fp32 ? fast_phase<float>(k, c, st, B, ldb, nrhs, phase)
+                    : fast_phase<double>(k, c, st, B, ldb, nrhs, phase);
     return c.fp32 ? leaf_phase<float>(c.nb, k, c, st, B, ldb, nrhs, phase)
                   : leaf_phase<double>(c.nb, k, c, st, B, ldb, nrhs, phase);
   };

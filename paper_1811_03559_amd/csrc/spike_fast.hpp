@@ -1,0 +1,370 @@
+// Leaf kernels built on the MFMA tile engine (non-pivoting factors).
+//
+// Factor stage, middle partitions (the three full sweeps of Table tab:sweeps):
+//   k_ftip_w : G_W = L^{-1} [C^_i; 0]            (forward, kl columns)
+//   k_ftip_u : [V W] = U^{-1} [L^{-1}[0; B^_i]  G_W], keeping only the top ku
+//              and bottom kl rows (the spike tips), written straight to the
+//              node tips.
+// Solve stage (one workgroup per partition, up to 64 right-hand sides): the
+// same stages as k_leaf_dstage / k_leaf_retrieve / k_leaf_zsweep /
+// k_leaf_dtstage with every full sweep on the tile engine; the truncated
+// pieces use the workgroup routines with 16-wide panels.
+#pragma once
+#include "spike_kernels.hpp"
+#include "spike_tile.hpp"
+
+namespace spike {
+
+constexpr int FNB = 16;   // panel width of the small truncated sweeps in the fast kernels
+
+template <typename T>
+__device__ __forceinline__ int is_f64() { return sizeof(T) == 8 ? 1 : 0; }
+
+__device__ __forceinline__ TSrc tsrc(const void* p, int f64, int64_t rs, int64_t ld, int lo1, int hi1,
+                                     int lo2 = 0, int hi2 = 0, int csplit = 0, int clo = 0) {
+  TSrc s;
+  s.p = p;
+  s.f64 = f64;
+  s.rs = rs;
+  s.ld = ld;
+  s.lo1 = lo1;
+  s.hi1 = hi1;
+  s.lo2 = lo2;
+  s.hi2 = hi2;
+  s.csplit = csplit;
+  s.clo = clo;
+  return s;
+}
+
+__device__ __forceinline__ TDst tdst(void* p1, void* p2, int f64, int64_t rs, int64_t ld, int top, int bot, int m,
+                                     int sub = 0) {
+  TDst d;
+  d.p1 = p1;
+  d.p2 = p2;
+  d.f64 = f64;
+  d.rs = rs;
+  d.ld = ld;
+  d.top = top;
+  d.bot = bot;
+  d.m = m;
+  d.sub = sub;
+  return d;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* leaf_dinv(const KParams& k, const LeafDesc& L) {
+  return reinterpret_cast<const T*>(k.dinv) + L.dinv_off;
+}
+
+// Full read/write view of a leaf's right-hand side (frame aware).
+__device__ __forceinline__ TSrc rhs_src(const Mat<double>& X, int m, int lo = 0, int hi = -1) {
+  return tsrc(X.p, 1, X.rs, X.ld, lo, hi < 0 ? m : hi);
+}
+__device__ __forceinline__ TDst rhs_dst(const Mat<double>& X, int m, int sub = 0) {
+  return tdst(X.p, nullptr, 1, X.rs, X.ld, m, m, m, sub);
+}
+
+// ---------------------------------------------------------------- factor stage
+// 16 x 16 diagonal-block inverses of every partition's L and U.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_diag_inv(KParams k) {
+  const LeafDesc L = k.leaves[blockIdx.x];
+  BandAcc<T> A = leaf_band<T>(k, L);
+  T* dv = reinterpret_cast<T*>(k.dinv) + L.dinv_off;
+  diag_inverses<T>(A, dv, blockIdx.y * NT + threadIdx.x, gridDim.y * NT);
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_w(KParams k, int ncg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int li = 1 + blockIdx.x / ncg, cg = blockIdx.x % ncg;
+  const LeafDesc L = k.leaves[li];
+  BandAcc<T> A = leaf_band<T>(k, L);
+  const T* dv = leaf_dinv<T>(k, L);
+  const int m = L.m, kl = k.kl, ku = k.ku;
+  T* fs = reinterpret_cast<T*>(k.fscr) + L.fscr_off;
+  const double* ch = k.chat + (int64_t)(li - 1) * kl * kl;
+  TSrc src = tsrc(ch, 1, 1, kl, 0, kl);
+  TDst dst = tdst(fs + (int64_t)ku * m, nullptr, is_f64<T>(), 1, m, m, m, m);
+  tile_sweep<T, HT, OP_L_FWD>(A, dv, src, dst, 64 * cg, kl, lds);
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_u(KParams k, int ncg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int li = 1 + blockIdx.x / ncg, cg = blockIdx.x % ncg;
+  const LeafDesc L = k.leaves[li];
+  BandAcc<T> A = leaf_band<T>(k, L);
+  const T* dv = leaf_dinv<T>(k, L);
+  const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw;
+  const T* fs = reinterpret_cast<const T*>(k.fscr) + L.fscr_off;
+  // V columns hold L^{-1}[0; B^] only from row m - ku on (zero above)
+  TSrc src = tsrc(fs, is_f64<T>(), 1, m, 0, m, 0, 0, ku, m - ku);
+  double* tp = k.tips + (int64_t)li * kw * kw;
+  TDst dst = tdst(tp, tp + ku, 1, 1, kw, ku, m - kl, m);
+  tile_sweep<T, HT, OP_U_BWD>(A, dv, src, dst, 64 * cg, kw, lds);
+}
+
+// ---------------------------------------------------------------- solve stage
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fdstage(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  if (solve_idle(k)) return;
+  const int li = blockIdx.x;
+  const LeafDesc L = k.leaves[li];
+  const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw;
+  BandAcc<T> A = leaf_band<T>(k, L);
+  const T* dv = leaf_dinv<T>(k, L);
+  Mat<double> X = leaf_rhs(L, B, ldb);
+  double* nv = k.nodeval + (int64_t)li * kw * k.R;
+  tile_sweep<T, HT, OP_L_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+  if (L.type == LEAF_SINGLE) {
+    tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    return;
+  }
+  if (L.type == LEAF_MIDDLE) {
+    // U sweep over G (left in place for the retrieval); keep only the tips
+    tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), tdst(nv, nv + ku, 1, 1, kw, ku, m - kl, m), 0, nrhs, lds);
+    return;
+  }
+  const int klf = A.kl, r0 = m - klf;
+  double* scr = k.sscr + L.sscr_off;
+  Mat<double> Tm = make_mat(scr + m, (int64_t)1, k.sscr_ld, r0);
+  for (int idx = threadIdx.x; idx < klf * nrhs; idx += NT) {
+    int r = r0 + idx % klf, q = idx / klf;
+    Tm.at(r, q) = X.at(r, q);
+  }
+  __syncthreads();
+  wg_usweep<FNB, T>(A, Tm, nrhs, r0, lds);
+  for (int idx = threadIdx.x; idx < klf * nrhs; idx += NT) {
+    int r = r0 + idx % klf, q = idx / klf;
+    if (L.type == LEAF_FIRST) nv[(ku + (r - r0)) + (int64_t)q * kw] = Tm.at(r, q);
+    else nv[(m - 1 - r) + (int64_t)q * kw] = Tm.at(r, q);
+  }
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fretrieve(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  if (solve_idle(k)) return;
+  const int li = blockIdx.x;
+  const LeafDesc L = k.leaves[li];
+  if (L.type == LEAF_SINGLE) return;
+  const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw, R = k.R;
+  BandAcc<T> A = leaf_band<T>(k, L);
+  const T* dv = leaf_dinv<T>(k, L);
+  Mat<double> X = leaf_rhs(L, B, ldb);
+  if (L.type == LEAF_MIDDLE) {
+    double* scr = k.sscr + L.sscr_off;
+    Mat<double> S = make_mat(scr, (int64_t)1, k.sscr_ld);
+    const double* ch = k.chat + (int64_t)(li - 1) * kl * kl;
+    const double* bh = k.bhat + (int64_t)li * ku * ku;
+    const double* xb = k.xint + (int64_t)(li - 1) * kw * R;
+    const double* xt = k.xint + (int64_t)li * kw * R + kl;
+    for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
+      int r = idx % kl, q = idx / kl;
+      double acc = 0.0;
+      for (int c = 0; c < kl; ++c) acc += ch[r + (int64_t)c * kl] * xb[c + (int64_t)q * kw];
+      S.at(r, q) = acc;
+    }
+    for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
+      int r = idx % ku, q = idx / ku;
+      double acc = 0.0;
+      for (int c = 0; c < ku; ++c) acc += bh[r + (int64_t)c * ku] * xt[c + (int64_t)q * kw];
+      S.at(m - ku + r, q) = acc;
+    }
+    __syncthreads();
+    // G_i -= L^{-1} [C^ X_{i-1,b}; 0; B^ X_{i+1,t}], then one full U sweep
+    tile_sweep<T, HT, OP_L_FWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, kl, m - ku, m), rhs_dst(X, m, 1), 0, nrhs, lds);
+    tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    return;
+  }
+  const bool rev = L.type == LEAF_LAST;
+  const int klf = A.kl, kuf = rev ? kl : ku;
+  const int h = kuf;
+  const T* sd = reinterpret_cast<const T*>(k.side) + (rev ? (int64_t)k.side_ld * k.kmax : 0);
+  const double* xn = rev ? k.xint + (int64_t)(k.p - 2) * kw * R : k.xint + kl;
+  for (int idx = threadIdx.x; idx < h * nrhs; idx += NT) {
+    int r = idx % h, q = idx / h;
+    double acc = 0.0;
+    for (int c = 0; c < kuf; ++c) acc += (double)sd[r + (int64_t)c * k.side_ld] * xn[c + (int64_t)q * kw];
+    X.at(m - h + r, q) -= acc;
+  }
+  __syncthreads();
+  (void)klf;
+  tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fzsweep(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  if (solve_idle(k)) return;
+  const int li = blockIdx.x;
+  const LeafDesc L = k.leaves[li];
+  const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw, R = k.R;
+  BandAcc<T> A = leaf_band<T>(k, L);
+  const T* dv = leaf_dinv<T>(k, L);
+  Mat<double> X = leaf_rhs(L, B, ldb);
+  if (L.type == LEAF_SINGLE) {
+    tile_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    tile_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    return;
+  }
+  double* scr = k.sscr + L.sscr_off;
+  Mat<double> S = make_mat(scr, (int64_t)1, k.sscr_ld);
+  const bool rev = L.type == LEAF_LAST;
+  const int klf = A.kl, kuf = rev ? kl : ku;
+  const int top0 = L.type == LEAF_MIDDLE ? ku : 0;
+  // H = U^{-T} [0; F~; 0] into scratch
+  tile_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m, top0, m - klf), tdst(scr, nullptr, 1, 1, k.sscr_ld, m, m, m), 0,
+                               nrhs, lds);
+  if (L.type == LEAF_MIDDLE) {
+    double* zprev = k.ztip + (int64_t)(li - 1) * kw * R;       // top_kl(Z_i)
+    double* znext = k.ztip + (int64_t)li * kw * R + kl;        // bottom_ku(Z_i)
+    tile_sweep<T, HT, OP_LT_BWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, m), tdst(zprev, znext, 1, 1, kw, kl, m - ku, m),
+                                 0, nrhs, lds);
+    return;
+  }
+  const int rmin = m - kuf;
+  const int r0 = (max(rmin, 0) / FNB) * FNB;
+  Mat<double> Tm = make_mat(scr + m, (int64_t)1, k.sscr_ld, r0);
+  for (int idx = threadIdx.x; idx < (m - r0) * nrhs; idx += NT) {
+    int r = r0 + idx % (m - r0), q = idx / (m - r0);
+    Tm.at(r, q) = S.at(r, q);
+  }
+  __syncthreads();
+  wg_ltsweep<FNB, T>(A, Tm, nrhs, rmin, lds);
+  if (!rev) {
+    double* z = k.ztip + kl;
+    for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
+      int r = idx % ku, q = idx / ku;
+      z[r + (int64_t)q * kw] = Tm.at(m - ku + r, q);
+    }
+  } else {
+    double* z = k.ztip + (int64_t)(k.p - 2) * kw * R;
+    for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
+      int r = idx % kl, q = idx / kl;
+      z[r + (int64_t)q * kw] = Tm.at(m - 1 - r, q);
+    }
+  }
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fdtstage(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  if (solve_idle(k)) return;
+  const int li = blockIdx.x;
+  const LeafDesc L = k.leaves[li];
+  if (L.type == LEAF_SINGLE) return;
+  const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw, R = k.R;
+  BandAcc<T> A = leaf_band<T>(k, L);
+  const T* dv = leaf_dinv<T>(k, L);
+  Mat<double> X = leaf_rhs(L, B, ldb);
+  const double* nv = k.nodeval + (int64_t)li * kw * R;
+  if (L.type == LEAF_MIDDLE) {
+    for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
+      int r = idx % ku, q = idx / ku;
+      X.at(r, q) = nv[r + (int64_t)q * kw];
+    }
+    for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
+      int r = idx % kl, q = idx / kl;
+      X.at(m - kl + r, q) = nv[ku + r + (int64_t)q * kw];
+    }
+    __syncthreads();
+    tile_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    tile_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    return;
+  }
+  const bool rev = L.type == LEAF_LAST;
+  const int klf = A.kl;
+  double* scr = k.sscr + L.sscr_off;
+  Mat<double> S = make_mat(scr, (int64_t)1, k.sscr_ld);
+  const int r0 = m - klf;
+  Mat<double> Tm = make_mat(scr + m, (int64_t)1, k.sscr_ld, r0);
+  for (int idx = threadIdx.x; idx < klf * nrhs; idx += NT) {
+    int r = r0 + idx % klf, q = idx / klf;
+    Tm.at(r, q) = rev ? nv[(m - 1 - r) + (int64_t)q * kw] : nv[ku + (r - r0) + (int64_t)q * kw];
+  }
+  __syncthreads();
+  wg_utsweep<FNB, T>(A, Tm, nrhs, r0, lds);
+  for (int idx = threadIdx.x; idx < m * nrhs; idx += NT) {
+    int r = idx % m, q = idx / m;
+    double v = S.at(r, q);
+    if (r >= r0) v += Tm.at(r, q);
+    X.at(r, q) = v;
+  }
+  __syncthreads();
+  tile_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+}
+
+// ---------------------------------------------------------------- runners
+template <typename K>
+inline void allow_lds_f(K kernel, size_t lds) {
+  hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T, int HT>
+int run_fast_factor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  {
+    ProfScope ps("k_diag_inv", st);
+    hipLaunchKernelGGL((k_diag_inv<T>), dim3(k.p, c.dinv_chunks), dim3(NT), 0, st, k);
+    SPIKE_CHECK_LAUNCH();
+  }
+  if (!k.fast_tips) return 0;
+  const int nmid = k.p - 2;
+  const int ncg_w = (k.kl + 63) / 64, ncg_u = (k.kw + 63) / 64;
+  allow_lds_f(k_ftip_w<T, HT>, c.fast_lds);
+  allow_lds_f(k_ftip_u<T, HT>, c.fast_lds);
+  if (ncg_w > 0) {
+    ProfScope ps("k_ftip_w", st);
+    hipLaunchKernelGGL((k_ftip_w<T, HT>), dim3(nmid * ncg_w), dim3(NT), c.fast_lds, st, k, ncg_w);
+    SPIKE_CHECK_LAUNCH();
+  }
+  {
+    ProfScope ps("k_ftip_u", st);
+    hipLaunchKernelGGL((k_ftip_u<T, HT>), dim3(nmid * ncg_u), dim3(NT), c.fast_lds, st, k, ncg_u);
+    SPIKE_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+template <typename T, int HT>
+int run_fast_phase(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
+                   int phase) {
+  switch (phase) {
+    case 0: {
+      allow_lds_f(k_fdstage<T, HT>, c.fast_lds);
+      ProfScope ps("k_fdstage", st);
+      hipLaunchKernelGGL((k_fdstage<T, HT>), dim3(k.p), dim3(NT), c.fast_lds, st, k, B, ldb, nrhs);
+      break;
+    }
+    case 1: {
+      allow_lds_f(k_fretrieve<T, HT>, c.fast_lds);
+      ProfScope ps("k_fretrieve", st);
+      hipLaunchKernelGGL((k_fretrieve<T, HT>), dim3(k.p), dim3(NT), c.fast_lds, st, k, B, ldb, nrhs);
+      break;
+    }
+    case 2: {
+      allow_lds_f(k_fzsweep<T, HT>, c.fast_lds);
+      ProfScope ps("k_fzsweep", st);
+      hipLaunchKernelGGL((k_fzsweep<T, HT>), dim3(k.p), dim3(NT), c.fast_lds, st, k, B, ldb, nrhs);
+      break;
+    }
+    default: {
+      allow_lds_f(k_fdtstage<T, HT>, c.fast_lds);
+      ProfScope ps("k_fdtstage", st);
+      hipLaunchKernelGGL((k_fdtstage<T, HT>), dim3(k.p), dim3(NT), c.fast_lds, st, k, B, ldb, nrhs);
+      break;
+    }
+  }
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
+}  // namespace spike

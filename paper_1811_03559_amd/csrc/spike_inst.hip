@@ -1,6 +1,7 @@
 // One translation unit per group of kernel instantiations, selected by the
 // build with -DSPIKE_INST_LEAF (with SPIKE_NB, SPIKE_T), -DSPIKE_INST_MERGE
 // (with SPIKE_NB) or -DSPIKE_INST_COMMON, so the kernels compile in parallel.
+#include "spike_fast.hpp"
 #include "spike_kernels.hpp"
 
 namespace spike {
@@ -12,6 +13,10 @@ template int run_leaf_phase<SPIKE_NB, SPIKE_T>(const KParams&, const LaunchCfg&,
 #elif defined(SPIKE_INST_MERGE)
 template int run_merge_factor<SPIKE_NB>(const KParams&, const LaunchCfg&, hipStream_t);
 template int run_merge_solve<SPIKE_NB>(const KParams&, const LaunchCfg&, hipStream_t, int, bool);
+#elif defined(SPIKE_INST_FAST)
+template int run_fast_factor<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t);
+template int run_fast_phase<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, double*, int64_t,
+                                                int, int);
 #elif defined(SPIKE_INST_COMMON)
 int run_init_status(DevStatus* s, hipStream_t st) {
   hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, s);

@@ -165,6 +165,24 @@ __global__ __launch_bounds__(NT) void k_leaf_factor(KParams k) {
   const int kl = k.kl, ku = k.ku, kw = k.kw;
   T* fs = reinterpret_cast<T*>(k.fscr) + L.fscr_off;   // m x kw, ld m
   Tips tips{k.tips, kw, ku};
+  if (L.type == LEAF_MIDDLE && k.fast_tips) {
+    // Only the truncated L sweep of V here; the full sweeps run on the tile
+    // engine afterwards.  L^{-1}[0; B^] is zero above row m - ku.
+    const int jv = (max(m - ku, 0) / NB) * NB;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)(m - jv) * ku; idx += NT) {
+      int r = jv + (int)(idx % (m - jv)), c = (int)(idx / (m - jv));
+      fs[r + (int64_t)c * m] = T(0);
+    }
+    __syncthreads();
+    const double* bh = k.bhat + (int64_t)li * ku * ku;
+    for (int idx = threadIdx.x; idx < ku * ku; idx += NT) {
+      int r = idx % ku, c = idx / ku;
+      fs[(m - ku + r) + (int64_t)c * m] = (T)bh[idx];
+    }
+    __syncthreads();
+    wg_lsweep<NB, T>(A, make_mat(fs, (int64_t)1, (int64_t)m), ku, jv, lds);
+    return;
+  }
   if (L.type == LEAF_MIDDLE) {
     // V RHS [0; B^_i] in columns [0, ku), W RHS [C^_i; 0] in columns [ku, kw).
     for (int64_t idx = threadIdx.x; idx < (int64_t)m * kw; idx += NT) fs[idx] = T(0);

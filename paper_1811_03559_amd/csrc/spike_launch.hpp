@@ -50,6 +50,8 @@ struct KParams {
   double* crl;
   double* sscr;
   const int32_t* skip;   // when non-null and *skip != 0 the solve kernels idle
+  int fast_tips;         // middle-partition tips are formed by the MFMA tile kernels
+  void* dinv;            // 16 x 16 diagonal-block inverses of L and U (T), tile engine
 };
 
 struct LaunchCfg {
@@ -57,7 +59,18 @@ struct LaunchCfg {
   bool fp32;
   size_t leaf_lds, merge_lds;
   std::vector<int> level_off;
+  bool fast;             // MFMA tile engine usable (non-pivoting, bandwidth <= 256)
+  int ht;                // its window height in 16-row tiles
+  size_t fast_lds;
+  int fast_min_nrhs;     // solves with at least this many columns use it
+  int dinv_chunks;       // grid.y of the diagonal-inverse kernel
 };
+
+template <typename T, int HT>
+int run_fast_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);
+template <typename T, int HT>
+int run_fast_phase(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
+                   int phase);
 
 // Runners, instantiated per panel width / precision in spike_inst.hip.
 template <int NB, typename T>

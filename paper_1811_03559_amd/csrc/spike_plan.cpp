@@ -118,6 +118,17 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
   }
   if (pl.nb_dense == 0) return -4;
   pl.merge_lds = std::max<size_t>(leaf_lds_elems(pl.nb_dense, kd, kd) * 8, 2 * 64 * 17 * 8) + 2048;
+  // MFMA tile engine: window heights of 1, 2, 4, 8, 10 or 16 tiles of 16 rows
+  pl.fast = false;
+  if (!o.pivot) {
+    for (int h : {1, 2, 4, 8, 10, 16})
+      if (16 * h >= pl.kmax) { pl.ht = h; pl.fast = true; break; }
+  }
+  if (pl.fast) {
+    size_t tile = (size_t)(2 * (pl.ht + 1) * 16 * 17);
+    pl.fast_lds = std::max(tile, leaf_lds_elems(16, pl.kmax, kuw_max)) * pl.tsize + 2048;
+    if (pl.fast_lds > 160 * 1024) pl.fast = false;
+  }
   if (pl.leaf_lds > 160 * 1024 || pl.merge_lds > 160 * 1024) return -4;
 
   // The last block is stored reversed (bandwidths swapped), so with pivoting
@@ -127,7 +138,7 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
 
   // ---- leaves
   pl.leaves.resize(p);
-  int64_t start = 0, band = 0, piv = 0, fscr = 0, sscr = 0, lpan = 0;
+  int64_t start = 0, band = 0, piv = 0, fscr = 0, sscr = 0, lpan = 0, dinv = 0;
   pl.lpld = o.pivot ? pl.nb + pl.kmax : 0;
   size_t R = (size_t)pl.nrhs_max;
   size_t extra_rows = (size_t)pl.kw + 2 * (size_t)pl.nb;
@@ -140,6 +151,8 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
     L.type = p == 1 ? LEAF_SINGLE : (i == 0 ? LEAF_FIRST : (i == p - 1 ? LEAF_LAST : LEAF_MIDDLE));
     L.band_off = band;
     L.lp_off = lpan;
+    L.dinv_off = dinv;
+    if (pl.fast) dinv += (sz[i] + 15) / 16 * 512;
     L.ipiv_off = piv;
     L.fscr_off = fscr;
     L.sscr_off = sscr;
@@ -209,6 +222,7 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
   pl.off_contrib = take(sizeof(Contrib) * std::max<size_t>(1, pl.contrib.size()));
   pl.off_band = take((size_t)band * pl.tsize);
   pl.off_lpan = take((size_t)lpan * pl.tsize);
+  pl.off_dinv = take((size_t)dinv * pl.tsize);
   pl.off_ipiv = take(sizeof(int) * (size_t)std::max<int64_t>(1, piv));
   pl.off_bhat = take(8 * (size_t)nif * ku * ku);
   pl.off_chat = take(8 * (size_t)nif * kl * kl);

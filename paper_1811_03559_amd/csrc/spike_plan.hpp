@@ -29,6 +29,9 @@ struct Plan {
   int side_ld = 1;      // rows of a stored truncation side block
   int levels = 0;
   size_t leaf_lds = 0, merge_lds = 0;
+  bool fast = false;    // MFMA tile engine for the full sweeps (non-pivoting)
+  int ht = 0;           // its window height in 16-row tiles
+  size_t fast_lds = 0;
 
   std::vector<LeafDesc> leaves;
   std::vector<MergeDesc> merges;   // grouped by level, level 1 first
@@ -38,6 +41,7 @@ struct Plan {
 
   // Workspace layout (byte offsets from the workspace base).
   size_t off_status = 0, off_leaves = 0, off_merges = 0, off_cptr = 0, off_contrib = 0;
+  size_t off_dinv = 0;
   size_t off_band = 0, off_lpan = 0, off_ipiv = 0, off_bhat = 0, off_chat = 0, off_side = 0;
   int64_t lpld = 0;    // leading dimension of a dense L panel tile (pivoting)
   size_t off_tips = 0, off_sfac = 0, off_spiv = 0, off_coef = 0, off_qw = 0;

@@ -144,15 +144,19 @@ __global__ void k_berr(DevStatus* st, unsigned long long* colred, int nrhs, int 
   if (threadIdx.x != 0 || st->skip) return;
   const double an = from_bits(trans ? st->anorm_one_bits : st->anorm_inf_bits);
   double berr = 0.0;
+  bool finite = true;
   for (int q = 0; q < nrhs; ++q) {
     double rm = from_bits(colred[2 * q]), xm = from_bits(colred[2 * q + 1]);
     double b = (an * xm) > 0.0 ? rm / (an * xm) : (rm > 0.0 ? __builtin_huge_val() : 0.0);
+    if (!__builtin_isfinite(rm) || !__builtin_isfinite(xm)) finite = false;
     berr = fmax(berr, b);
     colred[2 * q] = 0ull;
     colred[2 * q + 1] = 0ull;
   }
+  // a non-finite residual or solution is reported as NaN and ends the loop
+  if (!finite) berr = __builtin_nan("");
   st->berr = berr;
-  if (berr <= tol || it >= max_refine) st->skip = 1;
+  if (!finite || berr <= tol || it >= max_refine) st->skip = 1;
   else st->refine_iters = it + 1;
 }
 

@@ -19,6 +19,7 @@ struct LeafDesc {
   int64_t fscr_off;   // element offset of the factor-stage spike scratch (middle)
   int64_t sscr_off;   // double offset of the per-leaf solve scratch
   int64_t lp_off;     // element offset of the dense L panel tiles (pivoting)
+  int64_t dinv_off;   // element offset of the diagonal-block inverses (tile engine)
 };
 
 // A merge of two adjacent nodes L = [a..mif] and R = [mif+1..b] of the

@@ -183,3 +183,26 @@ def test_repeat_solve_is_bitwise_deterministic():
     B = torch.from_numpy(F.copy()).cuda()
     fac2.solve_(B)
     assert np.array_equal(outs[0], B.cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("pivot", [False, True])
+def test_workspace_prefilled_with_nan(precision, trans, pivot):
+    """Regression: the truncated U^T sweep of the first and last partitions
+    starts mid-panel; rows of that panel above its start must not be read
+    from stale memory.  The caching allocator is first filled with NaN so the
+    workspace starts as NaN; the result must still be finite and exact, and a
+    non-finite refinement residual is never reported as converged."""
+    import torch
+    n, k, p = 20000, 16, 8
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(inputs.seed_for(3)), diag_mult_range=(1.01, 1.5))
+    X_true = inputs.rhs(n, 3, inputs.rng_for(3))
+    F = oracle.gbmv(ab, k, k, X_true, trans=trans)
+    junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64, device="cuda")
+    del junk
+    X, info, _ = run(ab, k, k, F, trans=trans, p=p, pivot=pivot, precision=precision)
+    assert info["info"] == 0
+    if precision == "mixed":
+        assert np.isfinite(info["berr"]) and info["berr"] <= 1e-13, info
+    check(ab, k, k, F, X, trans=trans, pivot=pivot, X_true=X_true)
