@@ -63,28 +63,134 @@ def relres(ab, kl, ku, X, F, trans=False):
     return float(np.abs(r).max() / (A_inf * np.abs(X).max()))
 
 
-def leaf_work(sizes, k, nrhs):
-    """Algorithmic work of the partition kernels.
+def merge_tree(p):
+    """Leaf ranges (a, b) of every merge: adjacent nodes are paired left to
+    right at each level, an odd last node is carried up unchanged."""
+    nodes = [(i, i) for i in range(p)]
+    out = []
+    while len(nodes) > 1:
+        nxt = []
+        for j in range(0, len(nodes) - 1, 2):
+            a, b = nodes[j][0], nodes[j + 1][1]
+            out.append((a, b))
+            nxt.append((a, b))
+        if len(nodes) % 2:
+            nxt.append(nodes[-1])
+        nodes = nxt
+    return out
 
-    Factor kernel (flops): block LU 2 m k^2 per partition; the middle
-    partitions add the W spike L sweep (2 m k^2) and the [V W] U sweep
-    (2 m k (2k)) -> 8 m k^2 per middle partition, 2 m k^2 for first/last.
-    Solve kernels (bytes): each full sweep streams half the band (k+1 of the
-    2k+1 diagonals, 8 bytes each) plus the right-hand side in and out; per
-    solve the middle partitions make 4 full sweeps and first/last 2 (the
-    paper's Table tab:sweeps), split 2/2 (middle) and 1/1 between the two
-    kernels of the solve."""
+
+def step_work(sizes, k, nrhs, fast_tips):
+    """Algorithmic work of the kernels of one step (kl = ku = k).
+
+    Factor:
+      k_leaf_factor  block LU, 2 m k^2 flops per partition (plus, without the
+                     tile-engine tips, the spike sweeps: W L-sweep 2 m k^2 and
+                     [V W] U-sweep 4 m k^2 per middle partition);
+      k_ftip_w       W spike L-sweep, 2 m k^2 per middle partition;
+      k_ftip_u       [V W] U-sweep, 4 m k^2 per middle partition;
+      k_merge_factor per merge: Schur complement S = I - W_t V_b (2k^3), LU of
+                     S (2/3 k^3), alpha/beta (2k^3 sweeps + 2k^3 product) when
+                     the node has a right neighbour, gamma/delta (6k^3) when it
+                     has a left one, merged tips 2k^3 each (not at the root).
+    Solve (bytes, nrhs = 1 is bandwidth bound): each full sweep streams half
+    the band (k+1 of the 2k+1 diagonals, 8 bytes each); per solve the middle
+    partitions make 4 full sweeps and first/last 2 (the paper's sweep table),
+    split 2/2 and 1/1 between the two partition kernels of a solve, each of
+    which also reads and writes the right-hand side once (16 bytes a row per
+    column)."""
     p = len(sizes)
+    n = sum(sizes)
     mid = sum(sizes[1:-1]) if p > 2 else 0
-    ends = sum(sizes) - mid
+    ends = n - mid
     band_half = 8.0 * (k + 1)
-    return {
-        "k_leaf_factor": {"flops": 8.0 * mid * k * k + 2.0 * ends * k * k},
-        "k_leaf_dstage": {"bytes": (2 * mid + ends) * band_half + 16.0 * (mid + ends) * nrhs},
-        "k_leaf_retrieve": {"bytes": (2 * mid + ends) * band_half + 16.0 * (mid + ends) * nrhs},
-        "k_leaf_zsweep": {"bytes": (2 * mid + ends) * band_half + 16.0 * (mid + ends) * nrhs},
-        "k_leaf_dtstage": {"bytes": (2 * mid + ends) * band_half + 16.0 * (mid + ends) * nrhs},
+    k3 = float(k) ** 3
+    mflops = 0.0
+    for a, b in merge_tree(p):
+        nv, nw = b < p - 1, a > 0
+        f = 2 * k3 + (2.0 / 3.0) * k3
+        if nv:
+            f += 4 * k3
+        if nw:
+            f += 6 * k3
+        if not (a == 0 and b == p - 1):
+            f += 2 * k3 * ((nv and nw) * 2 + nv + nw)
+        mflops += f
+    sweep = (2 * mid + ends) * band_half + 16.0 * n * nrhs
+    w = {
+        "k_leaf_factor": {"flops": 2.0 * n * k * k + (0.0 if fast_tips else 6.0 * mid * k * k)},
+        "k_merge_factor": {"flops": mflops},
+        "k_leaf_dstage": {"bytes": sweep},
+        "k_leaf_retrieve": {"bytes": sweep},
+        "k_leaf_zsweep": {"bytes": sweep},
+        "k_leaf_dtstage": {"bytes": sweep},
     }
+    if fast_tips:
+        w["k_ftip_w"] = {"flops": 2.0 * mid * k * k, "engine": "mfma"}
+        w["k_ftip_u"] = {"flops": 4.0 * mid * k * k, "engine": "mfma"}
+    return w
+
+
+def calib_copy(gib=1.0, reps=3):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8,
+                      "reps": reps}), flush=True)
+
+
+def kernel_source_digest():
+    """SHA-256 over the library's kernel sources (names and bytes, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1811_03559_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    no record for this workload or the kernel sources changed since it was
+    taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(workload)
+    if not rec or rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    t = rec["per_dispatch"].get(kernel)
+    return None if t is None else t["read_bytes"] + t["write_bytes"]
+
+
+def roofline(name, work, timing, steps, workload):
+    """Roofline entry of one kernel: algorithmic work per launch over its
+    average launch time (launches of one step may differ in size, so the
+    per-step work over the per-step time is used; for one launch a step the
+    two agree)."""
+    traffic = measured_traffic(name, workload)
+    if work is None:
+        return {"kernel": name, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": None, "traffic": traffic}
+    t_step = timing["ms_per_step"] / 1000.0
+    if "flops" in work:
+        ach = work["flops"] / t_step / 1e12
+        return {"kernel": name, "bound": work.get("engine", "alu"), "achieved": ach,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                "traffic": traffic, "work_per_step": work["flops"]}
+    ach = work["bytes"] / t_step / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "work_per_step": work["bytes"]}
 
 
 def cpu_baseline(k, n_full, n_sample=150_000):
@@ -113,11 +219,16 @@ def main():
     ap.add_argument("--p", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-detail", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
+        return
 
     import torch
     from paper_1811_03559_amd import inputs, spike
@@ -160,25 +271,13 @@ def main():
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
 
     # roofline of the kernel with the largest share of a step
-    work = leaf_work(plan["sizes"], k, 1)
+    fast_tips = k <= 256 and p >= 3          # non-pivoting FP64: tile-engine spike tips
+    work = step_work(plan["sizes"], k, 1, fast_tips)
     kernels = {name: {"calls": c, "avg_ms": ms / max(c, 1), "ms_per_step": ms / args.steps}
                for name, (c, ms) in prof.items()}
     dom = max(kernels, key=lambda nm: kernels[nm]["ms_per_step"])
-    roof = None
-    if dom in work:
-        avg_s = kernels[dom]["avg_ms"] / 1000.0
-        if "flops" in work[dom]:
-            ach = work[dom]["flops"] / avg_s / 1e12
-            roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None}
-        else:
-            ach = work[dom]["bytes"] / avg_s / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
-    else:
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": None, "traffic": None}
-
+    roof = roofline(dom, work.get(dom), kernels[dom], args.steps,
+                    "spike_step_n%d_k%d_p%d" % (n, k, p))
     detail = {"kernels": kernels, "generation_s": t_gen}
     if not args.no_detail:
         # phase times, checked results, solve bandwidth, nrhs = 64
