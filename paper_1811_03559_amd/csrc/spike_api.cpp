@@ -90,6 +90,7 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   k.sscr = at<double>(w, pl.off_sscr);
   k.fast_tips = (pl.fast && pl.p >= 3) ? 1 : 0;
   k.dinv = w + pl.off_dinv;
+  k.lu_done = 0;
 
   spike::LaunchCfg& c = h->cfg;
   c.nb = pl.nb;
@@ -102,6 +103,7 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   c.ht = pl.ht;
   c.fast_lds = pl.fast_lds;
   c.fast_min_nrhs = 2;
+  c.flu = pl.fast && !pl.pivot && pl.ht <= 10;
   {
     int maxm = 0;
     for (auto& L : pl.leaves) maxm = L.m > maxm ? L.m : maxm;

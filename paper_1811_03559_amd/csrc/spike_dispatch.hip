@@ -49,6 +49,17 @@ int fast_phase(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, 
   }
 }
 
+template <typename T>
+int flu(const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  switch (c.ht) {
+    case 1: return run_flu<T, 1>(k, c, st);
+    case 2: return run_flu<T, 2>(k, c, st);
+    case 4: return run_flu<T, 4>(k, c, st);
+    case 8: return run_flu<T, 8>(k, c, st);
+    default: return run_flu<T, 10>(k, c, st);
+  }
+}
+
 int merge_factor(int nbd, const KParams& k, const LaunchCfg& c, hipStream_t st) {
   switch (nbd) {
     case 32: return run_merge_factor<32>(k, c, st);
@@ -69,8 +80,14 @@ int merge_solve(int nbd, const KParams& k, const LaunchCfg& c, hipStream_t st, i
 
 int launch_init_status(DevStatus* s, hipStream_t st) { return run_init_status(s, st); }
 
-int launch_factor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
-  int e = c.fp32 ? leaf_factor<float>(c.nb, k, c, st) : leaf_factor<double>(c.nb, k, c, st);
+int launch_factor(const KParams& k0, const LaunchCfg& c, hipStream_t st) {
+  KParams k = k0;
+  int e;
+  if (c.flu) {
+    if ((e = c.fp32 ? flu<float>(k, c, st) : flu<double>(k, c, st))) return e;
+    k.lu_done = 1;
+  }
+  e = c.fp32 ? leaf_factor<float>(c.nb, k, c, st) : leaf_factor<double>(c.nb, k, c, st);
   if (e) return e;
   if (c.fast) {
     e = c.fp32 ? fast_factor<float>(k, c, st) : fast_factor<double>(k, c, st);

@@ -311,7 +311,7 @@ inline void allow_lds_f(K kernel, size_t lds) {
 
 template <typename T, int HT>
 int run_fast_factor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
-  {
+  if (!c.flu) {   // the MFMA block LU writes the inverses itself
     ProfScope ps("k_diag_inv", st);
     hipLaunchKernelGGL((k_diag_inv<T>), dim3(k.p, c.dinv_chunks), dim3(NT), 0, st, k);
     SPIKE_CHECK_LAUNCH();

@@ -1,0 +1,405 @@
+// Block LU of a banded partition on MFMA tiles (non-pivoting; the factor
+// stage of the central-concept subsection, A_i = L_i U_i, with the last
+// partition factored as the LU of its reversal, pivoting-UL subsection).
+//
+// The partition is cut into 16 x 16 tiles; with HT = ceil(max(kl, ku) / 16)
+// the active part of the right-looking elimination is a window of
+// (HT + 1) x (HT + 1) tiles that slides one tile down the diagonal per step.
+// A workgroup has NW = HT + 1 wavefronts; wavefront w owns the tile columns
+// C = w (mod NW) and keeps the HT + 1 window tiles of its current column in
+// MFMA accumulators, so a tile stays in registers from the moment it is read
+// from the caller's band until it is final.  Step j (column block j is the
+// panel):
+//   * every other wavefront, with its column C in the window:
+//       U_{j,C} = L_jj^{-1} A_{j,C}                       (row tile, stored)
+//       Z       = U_jj^{-1} U_{j,C}
+//       A_{i,C} -= A_{i,j} Z,  i = j+1 .. j+HT              (trailing update)
+//     and one of them also forms the L tile L_{j+c,j} = A_{j+c,j} U_jj^{-1}
+//     for the factor output; (A_{i,j} U_jj^{-1}) U_{j,C} = A_{i,j} Z, so the
+//     trailing update needs the panel's raw tiles only;
+//   * the wavefront that owns column j+1 finishes its own update first, then
+//     factors the next diagonal tile in registers (16 rank-1 steps with
+//     cross-lane shuffles) and forms the inverses of its unit-lower and upper
+//     triangles, which it publishes in the other LDS buffer together with
+//     its column's raw tiles: the panel of step j+1 overlaps the trailing
+//     update of step j, and one barrier ends a step.
+// The diagonal-tile inverses are also the ones the multi-RHS sweeps use, so
+// they are written out as the partition's diagonal-block inverses.
+//
+// Boosting (threshold tau * ||A_i||_1): the first pass factors without
+// boosting and accumulates the exact column sums of |A_i| as tiles are read;
+// if any pivot fell below the threshold, the partition is factored again with
+// boosting.  When no pivot is below the threshold the boosted factorisation
+// applies no boost, so the first pass is already its result.
+#pragma once
+#include "spike_fast.hpp"
+
+namespace spike {
+
+template <typename T>
+struct PivStats {
+  T minpiv;
+  int boosts;
+  int first_zero;
+};
+
+// An opaque copy of x: values derived from it are recomputed where they are
+// used instead of being hoisted out of the elimination loop and kept live.
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Orders one wavefront's LDS accesses across lanes: stores before it are
+// visible to loads after it (a wavefront's LDS operations execute in order;
+// the fences keep the compiler from moving accesses across the point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Uniform read of lane `src` (src uniform across the wavefront).
+template <typename T>
+__device__ __forceinline__ T lane_read(T v, int src) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  }
+}
+
+// LU (no interchanges) of one 16 x 16 tile held by one wavefront in the
+// accumulator layout, with the inverses of its unit-lower and upper factors.
+// a: in A, out L\U; xl: L^{-1}; xu: U^{-1} (same layout).  Rows at or beyond
+// `mrem` are padding (identity) and are left out of the statistics.
+// Pivot rows and columns are exchanged through `x` (16 * 17 + 48 elements of
+// LDS used by this wavefront only), with a wavefront-level sync between the
+// stores of a step and the loads that read them.
+template <typename T>
+__device__ __forceinline__ void lu_inv16(typename Mf<T>::v4& a, typename Mf<T>::v4& xl, typename Mf<T>::v4& xu,
+                                         T boost, int row0, int mrem, PivStats<T>& st, T* x) {
+  using M = Mf<T>;
+  constexpr int PADW = tile_pad();
+  const int lane = opaque(threadIdx.x & 63), cl = lane & 15, g = lane >> 4;
+  T* xrow = x;                 // row t of the working tile
+  T* xcol = x + 16 * PADW;     // column t of the working tile
+  T* xlr = xcol + 16;          // row t of L^{-1}
+  T* xuc = xlr + 16;           // column t of U^{-1}
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = M::row(lane, q);
+    xl[q] = (r == cl) ? T(1) : T(0);
+    xu[q] = (r == cl) ? T(1) : T(0);
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int tg = M::grp(t), tq = M::reg(t);
+    if (g == tg) {
+      xrow[t * PADW + cl] = a[tq];
+      xlr[cl] = xl[tq];
+    }
+    if (cl == t) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xcol[M::row(lane, q)] = a[q];
+    }
+    wave_lds_sync();
+    T urow = xrow[t * PADW + cl];   // U(t, cl): row t is final
+    T piv = xrow[t * PADW + t];
+    const T xlt = xlr[cl];          // row t of L^{-1} is final
+    if (t < mrem) {
+      if (boost > T(0) && fabs(piv) < boost) {
+        piv = piv >= T(0) ? piv + boost : piv - boost;
+        st.boosts++;
+      }
+      st.minpiv = fmin(st.minpiv, (T)fabs(piv));
+      if (piv == T(0) && st.first_zero < 0) st.first_zero = row0 + t;
+    }
+    if (cl == t) urow = piv;
+    if (g == tg && cl == t) a[tq] = piv;
+    const T rp = piv != T(0) ? T(1) / piv : T(0);
+    if (cl == t) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xu[q] *= rp;                           // column t of U^{-1}
+        xuc[M::row(lane, q)] = xu[q];
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = M::row(lane, q);
+      const T lt = xcol[r];    // A(r, t)
+      const T xut = xuc[r];    // U^{-1}(r, t)
+      if (r > t) {
+        const T l = lt * rp;
+        if (cl == t) a[q] = l;
+        else if (cl > t) a[q] -= l * urow;
+        xl[q] -= l * xlt;
+      }
+      if (cl > t) xu[q] -= xut * urow;
+    }
+    wave_lds_sync();   // this step's loads before the next step's stores
+  }
+}
+
+// The elimination of one partition; REV: the partition is the last one,
+// held as the LU of its reversal (row and column order reversed).
+template <typename T, int HT, bool REV>
+__device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T* lds) {
+  using M = Mf<T>;
+  using v4 = typename M::v4;
+  constexpr int NW = HT + 1;
+  constexpr int PADW = tile_pad();
+  constexpr int TS = 16 * PADW;          // one tile in LDS
+  constexpr int BUF = (HT + 2) * TS;     // L^{-1}, U^{-1}, raw panel tiles 1..HT
+  T* xlu = lds + 2 * BUF;                // exchange area of the diagonal-tile LU
+  __shared__ double s_norm[NW];
+  __shared__ double s_minp[NW];
+  __shared__ int s_boost[NW], s_zero[NW];
+
+  const int m = L.m;
+  const BandAcc<T> A = leaf_band<T>(k, L);
+  T* dv = reinterpret_cast<T*>(k.dinv) + L.dinv_off;
+  const int klf = A.kl, kuf = A.kuw;
+  const int64_t s = L.start;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
+  constexpr int DQ = sizeof(T) == 8 ? 4 : 1;   // row step between registers
+  const int nbk = (m + 15) / 16;
+
+  // tile (R, C) of the block in the accumulator layout; entries outside the
+  // order are the identity, entries outside the band zero; `cs` gathers
+  // |a| of the real entries (this lane's rows of its column).  Element
+  // (i, c) of the block is A(s+i, s+c), or A(s+m-1-i, s+m-1-c) reversed.
+  auto load_tile = [&](int R, int Cc, double& cs) __attribute__((always_inline)) -> v4 {
+    const int ln = opaque(lane);
+    const int c = 16 * Cc + (ln & 15), i0 = 16 * R + M::row(ln, 0);
+    const int64_t gc = REV ? s + m - 1 - c : s + c;
+    const double* colp = k.dAB + (int64_t)k.ku + gc * k.ldab - gc + (REV ? s + m - 1 : s);   // + gi
+    const double* p0 = REV ? colp - i0 : colp + i0;
+    v4 v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + DQ * q;
+      T xv;
+      if (i >= m || c >= m) {
+        xv = (i == c) ? T(1) : T(0);
+      } else if (i - c > klf || c - i > kuf) {
+        xv = T(0);
+      } else {
+        const double av = REV ? p0[-DQ * q] : p0[DQ * q];
+        xv = (T)av;
+        cs += fabs(av);
+      }
+      v[q] = xv;
+    }
+    return v;
+  };
+  auto store_band = [&](int R, int Cc, const v4& v) __attribute__((always_inline)) {
+    const int ln = opaque(lane);
+    const int c = 16 * Cc + (ln & 15), i0 = 16 * R + M::row(ln, 0);
+    T* p0 = A.a + (int64_t)kuf - c + (int64_t)c * A.ldw + i0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + DQ * q;
+      if (i < m && c < m && i - c <= klf && c - i <= kuf) p0[DQ * q] = v[q];
+    }
+  };
+  auto lds_put = [&](T* P, const v4& v) __attribute__((always_inline)) {
+    const int ln = opaque(lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[M::row(ln, q) * PADW + (ln & 15)] = v[q];
+  };
+  // d += P * b, P a 16 x 16 tile in LDS, b in accumulator layout
+  auto mm_lds_reg = [&](const T* P, const v4& b, v4 d) __attribute__((always_inline)) -> v4 {
+    const int ln = opaque(lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d = M::mma(P[(ln & 15) * PADW + M::row(ln, q)], b[q], d);
+    return d;
+  };
+  // P * Q, both tiles in LDS
+  auto mm_lds_lds = [&](const T* P, const T* Q) __attribute__((always_inline)) -> v4 {
+    v4 d = {T(0), T(0), T(0), T(0)};
+    const int ln = opaque(lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = M::row(ln, q);
+      d = M::mma(P[(ln & 15) * PADW + r], Q[r * PADW + (ln & 15)], d);
+    }
+    return d;
+  };
+
+  double anorm = 0.0;
+  PivStats<T> st;
+  for (int pass = 0; pass < 2; ++pass) {
+    const T boost = pass == 0 ? T(0) : (T)(k.boost_tau * anorm);
+    st.minpiv = T(__builtin_huge_val());
+    st.boosts = 0;
+    st.first_zero = -1;
+    double nmax = 0.0;
+
+    // panel of step jp: the caller owns column jp, acc[i] = tile (jp + i, jp)
+    // after the updates of steps < jp
+    auto panel = [&](int jp, T* Pn, v4 (&acc)[HT + 1], double cs) __attribute__((always_inline)) {
+      double t = cs;
+      t += __shfl_xor(t, 16);
+      t += __shfl_xor(t, 32);
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) t = fmax(t, __shfl_xor(t, off));
+      nmax = fmax(nmax, t);
+#pragma unroll
+      for (int i = 1; i <= HT; ++i) lds_put(Pn + (1 + i) * TS, acc[i]);
+      v4 xl, xu;
+      lu_inv16<T>(acc[0], xl, xu, boost, 16 * jp, m - 16 * jp, st, xlu);
+      lds_put(Pn, xl);
+      lds_put(Pn + TS, xu);
+      store_band(jp, jp, acc[0]);
+      T* D = dv + (int64_t)jp * dinv_stride();
+      const int ln = opaque(lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = M::row(ln, q);
+        D[r * 16 + (ln & 15)] = xl[q];
+        D[256 + r * 16 + (ln & 15)] = xu[q];
+      }
+    };
+
+    int C = wave;
+    v4 acc[HT + 1];
+    double cs = 0.0;
+#pragma unroll
+    for (int i = 0; i <= HT; ++i) acc[i] = C < nbk ? load_tile(i, C, cs) : v4{T(0), T(0), T(0), T(0)};
+    if (wave == 0) panel(0, lds, acc, cs);
+    __syncthreads();
+
+    for (int j = 0; j < nbk; ++j) {
+      const T* P = lds + (j & 1) * BUF;
+      const int c = C - j;   // window column of this wavefront's tiles
+      if (c == 0) {
+        // column j is final; take the column entering the window next step
+        C += NW;
+        cs = 0.0;
+        if (C < nbk) {
+#pragma unroll
+          for (int i = 0; i <= HT; ++i) acc[i] = load_tile(j + 1 + i, C, cs);
+        }
+      } else if (C < nbk) {
+        const v4 nxt = load_tile(j + 1 + HT, C, cs);
+        const bool next_panel = (c == 1) && (j + 1 < nbk);
+        if (next_panel) __builtin_amdgcn_s_setprio(2);
+        const v4 zero = {T(0), T(0), T(0), T(0)};
+        const v4 u = mm_lds_reg(P, acc[0], zero);        // U_{j,C}
+        store_band(j, C, u);
+        const v4 nz = -mm_lds_reg(P + TS, u, zero);      // -U_jj^{-1} U_{j,C}
+        if (j + c < nbk) store_band(j + c, j, mm_lds_lds(P + (1 + c) * TS, P + TS));   // L_{j+c,j}
+#pragma unroll
+        for (int i = 1; i <= HT; ++i) acc[i] = mm_lds_reg(P + (1 + i) * TS, nz, acc[i]);
+#pragma unroll
+        for (int i = 0; i < HT; ++i) acc[i] = acc[i + 1];
+        acc[HT] = nxt;
+        if (next_panel) {
+          panel(j + 1, lds + ((j + 1) & 1) * BUF, acc, cs);
+          __builtin_amdgcn_s_setprio(0);
+        }
+      }
+      __syncthreads();
+    }
+
+    if (lane == 0) {
+      s_norm[wave] = nmax;
+      s_minp[wave] = (double)st.minpiv;
+      s_boost[wave] = st.boosts;
+      s_zero[wave] = st.first_zero;
+    }
+    __syncthreads();
+    double minp = __builtin_huge_val();
+    int boosts = 0, fz = -1;
+    anorm = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      anorm = fmax(anorm, s_norm[w]);
+      minp = fmin(minp, s_minp[w]);
+      boosts += s_boost[w];
+      if (s_zero[w] >= 0 && (fz < 0 || s_zero[w] < fz)) fz = s_zero[w];
+    }
+    __syncthreads();
+    const bool redo = pass == 0 && k.boost_tau > 0.0 && (T)minp < (T)(k.boost_tau * anorm);
+    if (!redo) {
+      if (tid == 0) {
+        if (fz >= 0) {
+          const int64_t grow = REV ? s + m - 1 - fz : s + fz;
+          atomicMin(&k.status->zero_row, (unsigned long long)(grow + 1));
+        }
+        if (boosts) atomicAdd(&k.status->n_boosts, boosts);
+        atomicMin(&k.status->min_pivot_bits, dbits(minp));
+      }
+      break;
+    }
+  }
+}
+
+// LDS bytes of k_flu<T, HT>: two panel buffers and the diagonal-tile exchange.
+template <typename T, int HT>
+constexpr size_t flu_lds_bytes() {
+  return ((size_t)2 * (HT + 2) * 16 * tile_pad() + 16 * tile_pad() + 48) * sizeof(T);
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__((HT + 1) * 64) void k_flu(KParams k) {
+  constexpr int NW = HT + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int li = blockIdx.x;
+  const LeafDesc L = k.leaves[li];
+  const int m = L.m;
+  const BandAcc<T> A = leaf_band<T>(k, L);
+  const int klf = A.kl, kuf = A.kuw;
+  const int64_t s = L.start;
+  const int nthr = NW * 64, tid = threadIdx.x;
+
+  // coupling blocks: B^_i (rows s_{i+1}-ku.., cols s_{i+1}..) and C^_i
+  // (rows s_i.., cols s_i-kl..), in the normal frame
+  if (li < k.p - 1) {
+    double* bh = k.bhat + (int64_t)li * k.ku * k.ku;
+    const int64_t s1 = s + m;
+    for (int idx = tid; idx < k.ku * k.ku; idx += nthr) {
+      const int r = idx % k.ku, c = idx / k.ku;
+      const int64_t gi = s1 - k.ku + r, gc = s1 + c;
+      bh[idx] = (r >= c) ? k.dAB[(k.ku + gi - gc) + gc * k.ldab] : 0.0;
+    }
+  }
+  if (li > 0) {
+    double* ch = k.chat + (int64_t)(li - 1) * k.kl * k.kl;
+    for (int idx = tid; idx < k.kl * k.kl; idx += nthr) {
+      const int r = idx % k.kl, c = idx / k.kl;
+      const int64_t gi = s + r, gc = s - k.kl + c;
+      ch[idx] = (r <= c) ? k.dAB[(k.ku + gi - gc) + gc * k.ldab] : 0.0;
+    }
+  }
+  // band slots that lie outside the block (top-left and bottom-right corners)
+  for (int idx = tid; idx < kuf * kuf; idx += nthr) {
+    const int c = idx / kuf, sr = idx % kuf;
+    if (c < m && sr < kuf - c) A.a[sr + (int64_t)c * A.ldw] = T(0);
+  }
+  for (int idx = tid; idx < klf * (int)A.ldw; idx += nthr) {
+    const int c = m - 1 - idx / (int)A.ldw, sr = idx % (int)A.ldw;
+    if (c >= 0 && c + sr - kuf >= m) A.a[sr + (int64_t)c * A.ldw] = T(0);
+  }
+  if (L.type == LEAF_LAST) flu_body<T, HT, true>(k, L, lds);
+  else flu_body<T, HT, false>(k, L, lds);
+}
+
+template <typename T, int HT>
+int run_flu(const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  constexpr int NW = HT + 1;
+  const size_t lds = flu_lds_bytes<T, HT>();
+  hipFuncSetAttribute((const void*)k_flu<T, HT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ProfScope ps("k_flu", st);
+  hipLaunchKernelGGL((k_flu<T, HT>), dim3(k.p), dim3(NW * 64), lds, st, k);
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
+}  // namespace spike

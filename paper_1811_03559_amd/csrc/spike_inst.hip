@@ -2,6 +2,7 @@
 // build with -DSPIKE_INST_LEAF (with SPIKE_NB, SPIKE_T), -DSPIKE_INST_MERGE
 // (with SPIKE_NB) or -DSPIKE_INST_COMMON, so the kernels compile in parallel.
 #include "spike_fast.hpp"
+#include "spike_flu.hpp"
 #include "spike_kernels.hpp"
 
 namespace spike {
@@ -15,6 +16,9 @@ template int run_merge_factor<SPIKE_NB>(const KParams&, const LaunchCfg&, hipStr
 template int run_merge_solve<SPIKE_NB>(const KParams&, const LaunchCfg&, hipStream_t, int, bool);
 #elif defined(SPIKE_INST_FAST)
 template int run_fast_factor<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t);
+#if SPIKE_HT <= 10
+template int run_flu<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t);
+#endif
 template int run_fast_phase<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, double*, int64_t,
                                                 int, int);
 #elif defined(SPIKE_INST_COMMON)

@@ -101,62 +101,64 @@ __global__ __launch_bounds__(NT) void k_leaf_factor(KParams k) {
   const int64_t s = L.start;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 
-  // 1. copy the block into its frame (wave per column) and take ||A_i||_1.
-  double cmax = 0.0;
-  for (int c = wave; c < m; c += NWAVE) {
-    const int64_t gc = rev ? s + m - 1 - c : s + c;
-    double csum = 0.0;
-    for (int sr = lane; sr < k.ldw; sr += 64) {
-      const int i = c + sr - kuwf;
-      T v = T(0);
-      if (i >= 0 && i < m && i - c <= klf && c - i <= kuf) {
-        const int64_t gi = rev ? s + m - 1 - i : s + i;
-        const double a = k.dAB[(k.ku + gi - gc) + gc * k.ldab];
-        v = (T)a;
-        csum += fabs(a);
+  if (!k.lu_done) {
+    // 1. copy the block into its frame (wave per column) and take ||A_i||_1.
+    double cmax = 0.0;
+    for (int c = wave; c < m; c += NWAVE) {
+      const int64_t gc = rev ? s + m - 1 - c : s + c;
+      double csum = 0.0;
+      for (int sr = lane; sr < k.ldw; sr += 64) {
+        const int i = c + sr - kuwf;
+        T v = T(0);
+        if (i >= 0 && i < m && i - c <= klf && c - i <= kuf) {
+          const int64_t gi = rev ? s + m - 1 - i : s + i;
+          const double a = k.dAB[(k.ku + gi - gc) + gc * k.ldab];
+          v = (T)a;
+          csum += fabs(a);
+        }
+        A.a[sr + (int64_t)c * k.ldw] = v;
       }
-      A.a[sr + (int64_t)c * k.ldw] = v;
+      for (int off = 32; off > 0; off >>= 1) csum += __shfl_xor(csum, off);
+      cmax = fmax(cmax, csum);
     }
-    for (int off = 32; off > 0; off >>= 1) csum += __shfl_xor(csum, off);
-    cmax = fmax(cmax, csum);
-  }
-  if (lane == 0) sred[wave] = cmax;
+    if (lane == 0) sred[wave] = cmax;
 
-  // 2. coupling blocks: B^_i (rows s_{i+1}-ku.., cols s_{i+1}..) and
-  //    C^_i (rows s_i.., cols s_i-kl..), in the normal frame.
-  if (li < k.p - 1) {
-    double* bh = k.bhat + (int64_t)li * k.ku * k.ku;
-    const int64_t s1 = s + m;
-    for (int idx = threadIdx.x; idx < k.ku * k.ku; idx += NT) {
-      int r = idx % k.ku, c = idx / k.ku;
-      int64_t gi = s1 - k.ku + r, gc = s1 + c;
-      bh[idx] = (r >= c) ? k.dAB[(k.ku + gi - gc) + gc * k.ldab] : 0.0;
+    // 2. coupling blocks: B^_i (rows s_{i+1}-ku.., cols s_{i+1}..) and
+    //    C^_i (rows s_i.., cols s_i-kl..), in the normal frame.
+    if (li < k.p - 1) {
+      double* bh = k.bhat + (int64_t)li * k.ku * k.ku;
+      const int64_t s1 = s + m;
+      for (int idx = threadIdx.x; idx < k.ku * k.ku; idx += NT) {
+        int r = idx % k.ku, c = idx / k.ku;
+        int64_t gi = s1 - k.ku + r, gc = s1 + c;
+        bh[idx] = (r >= c) ? k.dAB[(k.ku + gi - gc) + gc * k.ldab] : 0.0;
+      }
     }
-  }
-  if (li > 0) {
-    double* ch = k.chat + (int64_t)(li - 1) * k.kl * k.kl;
-    for (int idx = threadIdx.x; idx < k.kl * k.kl; idx += NT) {
-      int r = idx % k.kl, c = idx / k.kl;
-      int64_t gi = s + r, gc = s - k.kl + c;
-      ch[idx] = (r <= c) ? k.dAB[(k.ku + gi - gc) + gc * k.ldab] : 0.0;
+    if (li > 0) {
+      double* ch = k.chat + (int64_t)(li - 1) * k.kl * k.kl;
+      for (int idx = threadIdx.x; idx < k.kl * k.kl; idx += NT) {
+        int r = idx % k.kl, c = idx / k.kl;
+        int64_t gi = s + r, gc = s - k.kl + c;
+        ch[idx] = (r <= c) ? k.dAB[(k.ku + gi - gc) + gc * k.ldab] : 0.0;
+      }
     }
-  }
-  __syncthreads();
-  double anorm1 = 0.0;
-  for (int w = 0; w < NWAVE; ++w) anorm1 = fmax(anorm1, sred[w]);
+    __syncthreads();
+    double anorm1 = 0.0;
+    for (int w = 0; w < NWAVE; ++w) anorm1 = fmax(anorm1, sred[w]);
 
-  // 3. block factorisation
-  T boost = T(0);
-  if (!k.pivot && k.boost_tau > 0.0) boost = (T)(k.boost_tau * anorm1);
-  LuStats st;
-  wg_lu<NB, T>(A, ipiv_w, boost, lds, st);
-  if (threadIdx.x == 0) {
-    if (st.first_zero >= 0) {
-      int64_t grow = rev ? s + m - 1 - st.first_zero : s + st.first_zero;
-      atomicMin(&k.status->zero_row, (unsigned long long)(grow + 1));
+    // 3. block factorisation
+    T boost = T(0);
+    if (!k.pivot && k.boost_tau > 0.0) boost = (T)(k.boost_tau * anorm1);
+    LuStats st;
+    wg_lu<NB, T>(A, ipiv_w, boost, lds, st);
+    if (threadIdx.x == 0) {
+      if (st.first_zero >= 0) {
+        int64_t grow = rev ? s + m - 1 - st.first_zero : s + st.first_zero;
+        atomicMin(&k.status->zero_row, (unsigned long long)(grow + 1));
+      }
+      if (st.boosts) atomicAdd(&k.status->n_boosts, st.boosts);
+      atomicMin(&k.status->min_pivot_bits, dbits(st.min_piv));
     }
-    if (st.boosts) atomicAdd(&k.status->n_boosts, st.boosts);
-    atomicMin(&k.status->min_pivot_bits, dbits(st.min_piv));
   }
   if (L.type == LEAF_SINGLE) return;
   __syncthreads();

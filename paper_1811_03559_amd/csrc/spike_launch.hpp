@@ -52,6 +52,7 @@ struct KParams {
   const int32_t* skip;   // when non-null and *skip != 0 the solve kernels idle
   int fast_tips;         // middle-partition tips are formed by the MFMA tile kernels
   void* dinv;            // 16 x 16 diagonal-block inverses of L and U (T), tile engine
+  int lu_done;           // the block factors are already in place (k_leaf_factor forms tips only)
 };
 
 struct LaunchCfg {
@@ -64,8 +65,11 @@ struct LaunchCfg {
   size_t fast_lds;
   int fast_min_nrhs;     // solves with at least this many columns use it
   int dinv_chunks;       // grid.y of the diagonal-inverse kernel
+  bool flu;              // block LU on MFMA tiles (non-pivoting, window height <= 10 tiles)
 };
 
+template <typename T, int HT>
+int run_flu(const KParams& k, const LaunchCfg& c, hipStream_t st);
 template <typename T, int HT>
 int run_fast_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);
 template <typename T, int HT>

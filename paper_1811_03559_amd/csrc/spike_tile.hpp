@@ -42,6 +42,9 @@ struct Mf<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int l, int i) { return (l >> 4) + 4 * i; }
+  // lane group (l / 16) and register of row t
+  __host__ __device__ static constexpr int grp(int t) { return t & 3; }
+  __host__ __device__ static constexpr int reg(int t) { return t >> 2; }
 };
 
 template <>
@@ -51,6 +54,8 @@ struct Mf<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int l, int i) { return 4 * (l >> 4) + i; }
+  __host__ __device__ static constexpr int grp(int t) { return t >> 2; }
+  __host__ __device__ static constexpr int reg(int t) { return t & 3; }
 };
 
 enum TileOp { OP_L_FWD = 0, OP_U_BWD = 1, OP_UT_FWD = 2, OP_LT_BWD = 3 };

@@ -49,7 +49,7 @@ def test_grid(p, kl, ku, trans, pivot):
     check(ab, kl, ku, F, X, trans=trans, pivot=pivot)
 
 
-@pytest.mark.parametrize("k", [32, 64, 160])
+@pytest.mark.parametrize("k", [32, 64, 160, 200])
 @pytest.mark.parametrize("p", [2, 5, 8])
 @pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("pivot", [False, True])
