@@ -102,7 +102,7 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   c.fast = pl.fast;
   c.ht = pl.ht;
   c.fast_lds = pl.fast_lds;
-  c.fast_min_nrhs = 2;
+  c.fast_min_nrhs = 1;
   c.flu = pl.fast && !pl.pivot && pl.ht <= 10;
   {
     int maxm = 0;

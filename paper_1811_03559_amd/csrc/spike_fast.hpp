@@ -11,6 +11,7 @@
 // pieces use the workgroup routines with 16-wide panels.
 #pragma once
 #include "spike_kernels.hpp"
+#include "spike_gemv.hpp"
 #include "spike_tile.hpp"
 
 namespace spike {
@@ -120,14 +121,14 @@ __global__ __launch_bounds__(NT) void k_fdstage(KParams k, double* B, int64_t ld
   const T* dv = leaf_dinv<T>(k, L);
   Mat<double> X = leaf_rhs(L, B, ldb);
   double* nv = k.nodeval + (int64_t)li * kw * k.R;
-  tile_sweep<T, HT, OP_L_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+  leaf_sweep<T, HT, OP_L_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
   if (L.type == LEAF_SINGLE) {
-    tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
     return;
   }
   if (L.type == LEAF_MIDDLE) {
     // U sweep over G (left in place for the retrieval); keep only the tips
-    tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), tdst(nv, nv + ku, 1, 1, kw, ku, m - kl, m), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), tdst(nv, nv + ku, 1, 1, kw, ku, m - kl, m), 0, nrhs, lds);
     return;
   }
   const int klf = A.kl, r0 = m - klf;
@@ -179,8 +180,8 @@ __global__ __launch_bounds__(NT) void k_fretrieve(KParams k, double* B, int64_t 
     }
     __syncthreads();
     // G_i -= L^{-1} [C^ X_{i-1,b}; 0; B^ X_{i+1,t}], then one full U sweep
-    tile_sweep<T, HT, OP_L_FWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, kl, m - ku, m), rhs_dst(X, m, 1), 0, nrhs, lds);
-    tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_L_FWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, kl, m - ku, m), rhs_dst(X, m, 1), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
     return;
   }
   const bool rev = L.type == LEAF_LAST;
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(NT) void k_fretrieve(KParams k, double* B, int64_t 
   }
   __syncthreads();
   (void)klf;
-  tile_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+  leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
 }
 
 template <typename T, int HT>
@@ -211,8 +212,8 @@ __global__ __launch_bounds__(NT) void k_fzsweep(KParams k, double* B, int64_t ld
   const T* dv = leaf_dinv<T>(k, L);
   Mat<double> X = leaf_rhs(L, B, ldb);
   if (L.type == LEAF_SINGLE) {
-    tile_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
-    tile_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
     return;
   }
   double* scr = k.sscr + L.sscr_off;
@@ -221,12 +222,12 @@ __global__ __launch_bounds__(NT) void k_fzsweep(KParams k, double* B, int64_t ld
   const int klf = A.kl, kuf = rev ? kl : ku;
   const int top0 = L.type == LEAF_MIDDLE ? ku : 0;
   // H = U^{-T} [0; F~; 0] into scratch
-  tile_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m, top0, m - klf), tdst(scr, nullptr, 1, 1, k.sscr_ld, m, m, m), 0,
+  leaf_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m, top0, m - klf), tdst(scr, nullptr, 1, 1, k.sscr_ld, m, m, m), 0,
                                nrhs, lds);
   if (L.type == LEAF_MIDDLE) {
     double* zprev = k.ztip + (int64_t)(li - 1) * kw * R;       // top_kl(Z_i)
     double* znext = k.ztip + (int64_t)li * kw * R + kl;        // bottom_ku(Z_i)
-    tile_sweep<T, HT, OP_LT_BWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, m), tdst(zprev, znext, 1, 1, kw, kl, m - ku, m),
+    leaf_sweep<T, HT, OP_LT_BWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, m), tdst(zprev, znext, 1, 1, kw, kl, m - ku, m),
                                  0, nrhs, lds);
     return;
   }
@@ -277,8 +278,8 @@ __global__ __launch_bounds__(NT) void k_fdtstage(KParams k, double* B, int64_t l
       X.at(m - kl + r, q) = nv[ku + r + (int64_t)q * kw];
     }
     __syncthreads();
-    tile_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
-    tile_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    leaf_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
     return;
   }
   const bool rev = L.type == LEAF_LAST;
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(NT) void k_fdtstage(KParams k, double* B, int64_t l
     X.at(r, q) = v;
   }
   __syncthreads();
-  tile_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+  leaf_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
 }
 
 // ---------------------------------------------------------------- runners

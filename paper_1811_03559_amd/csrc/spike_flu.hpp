@@ -59,19 +59,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Uniform read of lane `src` (src uniform across the wavefront).
-template <typename T>
-__device__ __forceinline__ T lane_read(T v, int src) {
-  if constexpr (sizeof(T) == 8) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
-  } else {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-  }
-}
-
 // LU (no interchanges) of one 16 x 16 tile held by one wavefront in the
 // accumulator layout, with the inverses of its unit-lower and upper factors.
 // a: in A, out L\U; xl: L^{-1}; xu: U^{-1} (same layout).  Rows at or beyond

@@ -1,0 +1,155 @@
+// Banded triangular sweep of a single right-hand side (non-pivoting factors).
+//
+// With one column the sweep is bound by streaming the band from HBM, so it is
+// organised as a sequence of matrix-vector products over 16-row blocks
+// instead of MFMA tiles.  The workgroup keeps a ring of RS = 16 (HT + 1) rows
+// in flight, one row per thread: the current block and the HT blocks below
+// it (in sweep order) that it still updates.  Per block step:
+//   1. the 16 threads whose rows form the current block publish their value
+//      w to LDS (one barrier);
+//   2. every wavefront forms x = D^{-1} w with the precomputed inverse of the
+//      16 x 16 diagonal block (each lane multiplies four entries, two
+//      cross-lane sums finish a row), so x needs no second barrier;
+//   3. every other thread subtracts its row of the coupling block times x
+//      (16 coefficients, prefetched PD steps ahead);
+//   4. the 16 threads of the current block move to the rows entering the
+//      ring and start their loads of those rows' right-hand side; a row's
+//      right-hand side is only combined with its accumulated update when the
+//      row becomes current, HT steps later, so no load latency lies on the
+//      chain of block steps.
+// Operations, as for the tile engine: L X (unit lower, forward), U X (upper,
+// backward), U^T X (forward) and L^T X (unit, backward).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "spike_tile.hpp"
+
+namespace spike {
+
+// LDS elements (of T) used by gemv_sweep.
+__host__ __device__ constexpr int gemv_lds_elems() { return 32; }
+
+template <typename T, int HT, int OP, typename Acc>
+__device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const TDst& dst, T* lds) {
+  constexpr bool FWD = (OP == OP_L_FWD || OP == OP_UT_FWD);
+  constexpr bool USE_U = (OP == OP_U_BWD || OP == OP_UT_FWD);
+  constexpr bool TRANS = (OP == OP_UT_FWD || OP == OP_LT_BWD);
+  constexpr int RS = 16 * (HT + 1);
+  // prefetch depth of coefficients and block inverses, in steps; a thread's
+  // row advances once every HT + 1 steps, so a prefetch PD + 1 <= HT + 1
+  // steps ahead sees at most one advance
+  constexpr int PD = HT < 2 ? HT : 2;
+  static_assert(RS <= NT, "ring larger than the workgroup");
+  const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, g4 = lane >> 4;
+  const int m = A.m, nb = (m + 15) / 16, mp = 16 * nb;
+  const bool act = tid < RS;
+  // band reach of the coupling entries
+  const int reach = (OP == OP_L_FWD || OP == OP_LT_BWD) ? A.kl : A.kuw;
+
+  auto row_of = [&](int pos) { return FWD ? pos : mp - 1 - pos; };
+  auto blk_of = [&](int s) { return FWD ? s : nb - 1 - s; };
+
+  int pos = tid;   // ring position of this thread's row (step 0 holds positions 0 .. RS-1)
+  T rhs = T(0), upd = T(0);
+  if (act && pos < mp) {
+    const int i = row_of(pos);
+    if (i < m) rhs = (T)src.load(i, 0);
+  }
+
+  // coefficients M(i, 16 b + c), c = 0..15, of this thread's row at step sp
+  auto fetch_cf = [&](int sp, T* cf) {
+    const int pp = pos >= 16 * sp ? pos : pos + RS;
+    const int i = row_of(pp);
+    const int b = blk_of(sp);
+    const bool ok = act && sp < nb && pp >= 16 * sp + 16 && pp < mp && i < m;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int cc = 16 * b + c;
+      const int d = FWD ? i - cc : cc - i;   // distance from the diagonal, > 0
+      T v = T(0);
+      if (ok && cc < m && d <= reach) {
+        v = TRANS ? A.a[(int64_t)(A.kuw + cc - i) + (int64_t)i * A.ldw]
+                  : A.a[(int64_t)(A.kuw + i - cc) + (int64_t)cc * A.ldw];
+      }
+      cf[c] = v;
+    }
+  };
+  // entries (r16, 4 g4 + c4) of the inverse of the diagonal block of step sp
+  auto fetch_dv = [&](int sp, T* dvv) {
+    const int b = blk_of(sp < nb ? sp : nb - 1);
+    const T* D = dinv + (int64_t)b * dinv_stride() + (USE_U ? 256 : 0);
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const int c = 4 * g4 + c4;
+      dvv[c4] = TRANS ? D[c * 16 + r16] : D[r16 * 16 + c];
+    }
+  };
+
+  T cf[PD + 1][16];
+  T dv[PD + 1][4];
+#pragma unroll
+  for (int d = 0; d <= PD; ++d) {
+    fetch_cf(d, cf[d]);
+    fetch_dv(d, dv[d]);
+  }
+
+  for (int s = 0; s < nb; ++s) {
+    const int b = blk_of(s);
+    T* wb = lds + (s & 1) * 16;
+    const bool cur = act && pos < 16 * s + 16;
+    if (cur) wb[row_of(pos) - 16 * b] = rhs - upd;
+    __syncthreads();
+    // x = D_b^{-1} w_b; lane holds x of row 16 b + r16
+    T xp = T(0);
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) xp += dv[0][c4] * wb[4 * g4 + c4];
+    xp += __shfl_xor(xp, 16);
+    xp += __shfl_xor(xp, 32);
+    if (tid < 16 && 16 * b + tid < m) dst.store(16 * b + tid, 0, (double)xp);
+    T xs[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) xs[c] = lane_read(xp, c);
+    if (act && !cur) {
+      T acc = upd;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc += cf[0][c] * xs[c];
+      upd = acc;
+    }
+    if (cur) {
+      pos += RS;
+      upd = T(0);
+      rhs = T(0);
+      if (pos < mp) {
+        const int i = row_of(pos);
+        if (i < m) rhs = (T)src.load(i, 0);
+      }
+    }
+    // rotate the prefetch rings and fetch step s + PD + 1
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) cf[d][c] = cf[d + 1][c];
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) dv[d][c4] = dv[d + 1][c4];
+    }
+    fetch_cf(s + PD + 1, cf[PD]);
+    fetch_dv(s + PD + 1, dv[PD]);
+  }
+  __syncthreads();   // the last block's LDS reads before the caller reuses LDS
+}
+
+// Full sweep of columns [c0, ncol) of a leaf on the tile engine, or on the
+// matrix-vector engine when it is a single column and the ring fits.
+template <typename T, int HT, int OP, typename Acc>
+__device__ __forceinline__ void leaf_sweep(const Acc& A, const T* dinv, const TSrc& src, const TDst& dst, int c0,
+                                           int ncol, T* lds) {
+  if constexpr (16 * (HT + 1) <= NT) {
+    if (ncol - c0 == 1 && c0 == 0) {
+      gemv_sweep<T, HT, OP>(A, dinv, src, dst, lds);
+      return;
+    }
+  }
+  tile_sweep<T, HT, OP>(A, dinv, src, dst, c0, ncol, lds);
+}
+
+}  // namespace spike

@@ -58,6 +58,19 @@ struct Mf<float> {
   __host__ __device__ static constexpr int reg(int t) { return t & 3; }
 };
 
+// Uniform read of lane `src` (src uniform across the wavefront).
+template <typename T>
+__device__ __forceinline__ T lane_read(T v, int src) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  }
+}
+
 enum TileOp { OP_L_FWD = 0, OP_U_BWD = 1, OP_UT_FWD = 2, OP_LT_BWD = 3 };
 
 // Source of the right-hand side: element (r, c) at p[r * rs + c * ld] for
