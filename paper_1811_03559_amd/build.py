@@ -48,6 +48,8 @@ def units() -> list[tuple[str, str, list[str]]]:
         for ht in HTS:
             u.append((f"fast_{t}_{ht}.o", "spike_inst.hip",
                       ["-DSPIKE_INST_FAST", f"-DSPIKE_T={t}", f"-DSPIKE_HT={ht}"]))
+    for ht in HTS:
+        u.append((f"mfast_{ht}.o", "spike_inst.hip", ["-DSPIKE_INST_MFAST", f"-DSPIKE_HT={ht}"]))
     u.append(("common.o", "spike_inst.hip", ["-DSPIKE_INST_COMMON"]))
     for src in ("spike_dispatch.hip", "spike_refine.hip", "spike_plan.cpp", "spike_api.cpp",
                 "spike_profile.cpp"):

@@ -91,6 +91,9 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   k.fast_tips = (pl.fast && pl.p >= 3) ? 1 : 0;
   k.dinv = w + pl.off_dinv;
   k.lu_done = 0;
+  k.sdinv = at<double>(w, pl.off_sdinv);
+  k.sperm = at<int>(w, pl.off_sperm);
+  k.mtmp = at<double>(w, pl.off_mtmp);
 
   spike::LaunchCfg& c = h->cfg;
   c.nb = pl.nb;
@@ -104,6 +107,8 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   c.fast_lds = pl.fast_lds;
   c.fast_min_nrhs = 1;
   c.flu = pl.fast && !pl.pivot && pl.ht <= 10;
+  c.mfast = pl.mfast;
+  c.mht = pl.mht;
   {
     int maxm = 0;
     for (auto& L : pl.leaves) maxm = L.m > maxm ? L.m : maxm;

@@ -60,6 +60,28 @@ int flu(const KParams& k, const LaunchCfg& c, hipStream_t st) {
   }
 }
 
+int mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  switch (c.mht) {
+    case 1: return run_mfactor<1>(k, c, st);
+    case 2: return run_mfactor<2>(k, c, st);
+    case 4: return run_mfactor<4>(k, c, st);
+    case 8: return run_mfactor<8>(k, c, st);
+    case 10: return run_mfactor<10>(k, c, st);
+    default: return run_mfactor<16>(k, c, st);
+  }
+}
+
+int msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, bool trans) {
+  switch (c.mht) {
+    case 1: return run_msolve<1>(k, c, st, nrhs, trans);
+    case 2: return run_msolve<2>(k, c, st, nrhs, trans);
+    case 4: return run_msolve<4>(k, c, st, nrhs, trans);
+    case 8: return run_msolve<8>(k, c, st, nrhs, trans);
+    case 10: return run_msolve<10>(k, c, st, nrhs, trans);
+    default: return run_msolve<16>(k, c, st, nrhs, trans);
+  }
+}
+
 int merge_factor(int nbd, const KParams& k, const LaunchCfg& c, hipStream_t st) {
   switch (nbd) {
     case 32: return run_merge_factor<32>(k, c, st);
@@ -93,7 +115,7 @@ int launch_factor(const KParams& k0, const LaunchCfg& c, hipStream_t st) {
     e = c.fp32 ? fast_factor<float>(k, c, st) : fast_factor<double>(k, c, st);
     if (e) return e;
   }
-  if (k.p > 1) return merge_factor(c.nb_dense, k, c, st);
+  if (k.p > 1) return c.mfast ? mfactor(k, c, st) : merge_factor(c.nb_dense, k, c, st);
   return 0;
 }
 
@@ -111,14 +133,14 @@ int launch_solve(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B
   if (!trans) {
     if ((e = leaf(0))) return e;            // D stage
     if (k.p > 1) {
-      if ((e = merge_solve(c.nb_dense, k, c, st, nrhs, false))) return e;
+      if ((e = c.mfast ? msolve(k, c, st, nrhs, false) : merge_solve(c.nb_dense, k, c, st, nrhs, false))) return e;
       if ((e = leaf(1))) return e;          // retrieval
     }
   } else {
     if ((e = leaf(2))) return e;            // Z sweeps of the transpose S stage
     if (k.p > 1) {
       if ((e = run_gform(k, st, B, ldb, nrhs))) return e;
-      if ((e = merge_solve(c.nb_dense, k, c, st, nrhs, true))) return e;
+      if ((e = c.mfast ? msolve(k, c, st, nrhs, true) : merge_solve(c.nb_dense, k, c, st, nrhs, true))) return e;
       if ((e = leaf(3))) return e;          // transpose D stage
     }
   }

@@ -68,8 +68,7 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
       const int d = FWD ? i - cc : cc - i;   // distance from the diagonal, > 0
       T v = T(0);
       if (ok && cc < m && d <= reach) {
-        v = TRANS ? A.a[(int64_t)(A.kuw + cc - i) + (int64_t)i * A.ldw]
-                  : A.a[(int64_t)(A.kuw + i - cc) + (int64_t)cc * A.ldw];
+        v = TRANS ? A.at(cc, i) : A.at(i, cc);
       }
       cf[c] = v;
     }

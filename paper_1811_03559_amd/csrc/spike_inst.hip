@@ -3,6 +3,7 @@
 // (with SPIKE_NB) or -DSPIKE_INST_COMMON, so the kernels compile in parallel.
 #include "spike_fast.hpp"
 #include "spike_flu.hpp"
+#include "spike_merge.hpp"
 #include "spike_kernels.hpp"
 
 namespace spike {
@@ -21,6 +22,9 @@ template int run_flu<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStr
 #endif
 template int run_fast_phase<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, double*, int64_t,
                                                 int, int);
+#elif defined(SPIKE_INST_MFAST)
+template int run_mfactor<SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t);
+template int run_msolve<SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, int, bool);
 #elif defined(SPIKE_INST_COMMON)
 int run_init_status(DevStatus* s, hipStream_t st) {
   hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, s);

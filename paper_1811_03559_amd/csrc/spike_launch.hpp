@@ -53,6 +53,9 @@ struct KParams {
   int fast_tips;         // middle-partition tips are formed by the MFMA tile kernels
   void* dinv;            // 16 x 16 diagonal-block inverses of L and U (T), tile engine
   int lu_done;           // the block factors are already in place (k_leaf_factor forms tips only)
+  double* sdinv;         // 16 x 16 diagonal-block inverses of S's L and U, per interface
+  int* sperm;            // row permutation of S's factorisation, per interface
+  double* mtmp;          // reduced-solve scratch, kw x R per interface
 };
 
 struct LaunchCfg {
@@ -66,8 +69,14 @@ struct LaunchCfg {
   int fast_min_nrhs;     // solves with at least this many columns use it
   int dinv_chunks;       // grid.y of the diagonal-inverse kernel
   bool flu;              // block LU on MFMA tiles (non-pivoting, window height <= 10 tiles)
+  bool mfast;            // reduced system on MFMA tiles
+  int mht;               // its sweep window height
 };
 
+template <int HT>
+int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st);
+template <int HT>
+int run_msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, bool trans);
 template <typename T, int HT>
 int run_flu(const KParams& k, const LaunchCfg& c, hipStream_t st);
 template <typename T, int HT>

@@ -1,0 +1,655 @@
+// Recursive reduced system on MFMA tiles (bandwidths up to 256).
+//
+// Every merge J = (L, R) of the tree owns the interface system
+// E_J = [[I, V_b(L)], [W_t(R), I]] (recursive-reduced-system subsection),
+// solved through its Schur complement S = I - W_t(R) V_b(L).  A level of the
+// tree is factored in five launches, each spread over all merges of the
+// level and over 32 x 32 output tiles (or 64-column groups):
+//   1. S = I - W_t(R) V_b(L)   and   Dm = -W_t(R) W_b(L)
+//   2. P S = L U (partial pivoting, one workgroup per merge), the 16 x 16
+//      diagonal-block inverses of L and U and the row permutation
+//   3. beta = S^{-1} V_t(R),  delta = S^{-1} Dm   (blocked substitution)
+//   4. alpha = -V_b(L) beta,  gamma = W_b(L) - V_b(L) delta
+//   5. the boundary tips of J: V_t = -V_t(L) beta, W_b = -W_b(R) gamma,
+//      V_b = V_b(R) - W_b(R) alpha, W_t = W_t(L) - V_t(L) delta.
+// The solve stage uses the same factors: right-hand sides are permuted, then
+// swept with L and U (or U^T, L^T and the inverse permutation).
+#pragma once
+#include "spike_gemv.hpp"
+#include "spike_kernels.hpp"
+
+namespace spike {
+
+// ---------------------------------------------------------------- GEMM jobs
+struct GJob {
+  int M, N, K, addI, on;
+  double alpha, beta;
+  const double* A;
+  int64_t ars, acs;
+  const double* B;
+  int64_t brs, bcs;
+  const double* Cin;
+  int64_t ldcin;
+  double* C;
+  int64_t ldc;
+};
+
+__host__ __device__ constexpr int mgemm_jobs(int ph) { return ph == 1 ? 2 : (ph == 4 ? 2 : 4); }
+
+// job `job` of phase `ph` of merge J; coef holds [alpha beta; gamma delta]
+// as a kw x kw block: alpha rows [0,kl) cols [0,ku), beta rows [kl,kw) cols
+// [0,ku), gamma rows [0,kl) cols [ku,kw), delta rows [kl,kw) cols [ku,kw).
+__device__ inline GJob merge_job(const KParams& k, const MergeDesc& J, int ph, int job) {
+  const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif;
+  const Tips tp{k.tips, kw, ku};
+  const bool nv = J.b < k.p - 1, nw = J.a > 0, root = J.a == 0 && J.b == k.p - 1;
+  double* C = k.coef + (int64_t)mi * kw * kw;
+  double* alpha = C;
+  double* beta = C + kl;
+  double* gamma = C + (int64_t)ku * kw;
+  double* delta = C + kl + (int64_t)ku * kw;
+  double* dm = k.qw + (int64_t)mi * kw * kw;   // -W_t(R) W_b(L), ku x kl, ld ku
+  const int jid = k.p + mi;
+  GJob g;
+  g.addI = 0;
+  g.on = 0;
+  g.alpha = -1.0;
+  g.beta = 0.0;
+  g.Cin = nullptr;
+  g.ldcin = 0;
+  g.ars = 1;
+  g.acs = kw;
+  g.brs = 1;
+  g.bcs = kw;
+  auto set = [&](int M, int N, int K, const double* A, const double* B, double* Cout, int64_t ldc) {
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.A = A;
+    g.B = B;
+    g.C = Cout;
+    g.ldc = ldc;
+  };
+  if (ph == 1) {
+    if (job == 0) {
+      set(ku, ku, kl, tp.Wt(J.right), tp.Vb(J.left), k.sfac + (int64_t)mi * ku * ku, ku);
+      g.addI = 1;
+      g.on = 1;
+    } else {
+      set(ku, kl, kl, tp.Wt(J.right), tp.Wb(J.left), dm, ku);
+      g.on = nw;
+    }
+  } else if (ph == 4) {
+    if (job == 0) {
+      set(kl, ku, ku, tp.Vb(J.left), beta, alpha, kw);
+      g.on = nv;
+    } else {
+      set(kl, kl, ku, tp.Vb(J.left), delta, gamma, kw);
+      g.Cin = tp.Wb(J.left);
+      g.ldcin = kw;
+      g.beta = 1.0;
+      g.on = nw;
+    }
+  } else {
+    if (job == 0) {
+      set(ku, ku, ku, tp.Vt(J.left), beta, tp.Vt(jid), kw);
+      g.on = nv && nw;
+    } else if (job == 1) {
+      set(kl, kl, kl, tp.Wb(J.right), gamma, tp.Wb(jid), kw);
+      g.on = nv && nw;
+    } else if (job == 2) {
+      set(kl, ku, kl, tp.Wb(J.right), alpha, tp.Vb(jid), kw);
+      g.Cin = tp.Vb(J.right);
+      g.ldcin = kw;
+      g.beta = 1.0;
+      g.on = nv;
+    } else {
+      set(ku, kl, ku, tp.Vt(J.left), delta, tp.Wt(jid), kw);
+      g.Cin = tp.Wt(J.left);
+      g.ldcin = kw;
+      g.beta = 1.0;
+      g.on = nw;
+    }
+    if (root) g.on = 0;
+  }
+  return g;
+}
+
+// LDS doubles of k_mgemm for inner dimension up to kmax.
+__host__ __device__ constexpr int mgemm_lds_elems(int kmax) {
+  return 32 * (((kmax + 3) & ~3) + 1) + ((kmax + 3) & ~3) * 33;
+}
+
+// One 32 x 32 output tile of one GEMM job per workgroup:
+//   C = beta Cin + alpha A B (+ I), A and B staged whole into LDS.
+template <int PH>
+__global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj) {
+  using M = Mf<double>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  constexpr int NJ = mgemm_jobs(PH);
+  const int tile = blockIdx.x % tpj, rest = blockIdx.x / tpj;
+  const int job = rest % NJ, mm = rest / NJ;
+  const MergeDesc J = k.merges[mbeg + mm];
+  const GJob g = merge_job(k, J, PH, job);
+  if (!g.on) return;
+  const int tm = (g.M + 31) / 32, tn = (g.N + 31) / 32;
+  if (tile >= tm * tn) return;
+  const int i0 = (tile % tm) * 32, j0 = (tile / tm) * 32;
+  const int Kp = (g.K + 3) & ~3, pa = Kp + 1;
+  double* As = lds;              // As[i * pa + kk]
+  double* Bs = lds + 32 * pa;    // Bs[kk * 33 + j]
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < 32 * Kp; idx += NT) {
+    const int i = idx % 32, kk = idx / 32;
+    const int gi = i0 + i;
+    As[i * pa + kk] = (gi < g.M && kk < g.K) ? g.A[(int64_t)gi * g.ars + (int64_t)kk * g.acs] : 0.0;
+  }
+  for (int idx = tid; idx < 32 * Kp; idx += NT) {
+    const int kk = idx % Kp, j = idx / Kp;
+    const int gj = j0 + j;
+    Bs[kk * 33 + j] = (gj < g.N && kk < g.K) ? g.B[(int64_t)kk * g.brs + (int64_t)gj * g.bcs] : 0.0;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, wi = wave & 1, wj = wave >> 1, cl = lane & 15, kq = lane >> 4;
+  M::v4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k4 = 0; k4 < Kp; k4 += 4)
+    acc = M::mma(As[(wi * 16 + cl) * pa + k4 + kq], Bs[(k4 + kq) * 33 + wj * 16 + cl], acc);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + wi * 16 + M::row(lane, q), j = j0 + wj * 16 + cl;
+    if (i < g.M && j < g.N) {
+      double v = g.alpha * acc[q];
+      if (g.Cin) v += g.beta * g.Cin[i + (int64_t)j * g.ldcin];
+      if (g.addI && i == j) v += 1.0;
+      g.C[i + (int64_t)j * g.ldc] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- LU of S
+// LDS doubles of k_mlu for order n.
+__host__ __device__ constexpr int mlu_lds_elems(int n) { return n * 17 + n * 17 + 16; }
+
+// P S = L U with partial pivoting (ties to the smallest row), interchanges
+// applied to whole rows; then the row permutation perm (row i of P S is row
+// perm[i] of S) and the 16 x 16 diagonal-block inverses of L and U.
+static __global__ __launch_bounds__(NT) void k_mlu(KParams k, int mbeg) {
+  using Mq = Mf<double>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  __shared__ int s_pl[256];     // panel-local row permutation
+  __shared__ int s_mv[64];      // rows that move: destination, then source
+  __shared__ int s_nmv;
+  __shared__ int s_zero;
+  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const int n = k.ku, mi = J.mif;
+  double* S = k.sfac + (int64_t)mi * n * n;
+  int* ipiv = k.spiv + (int64_t)mi * n;
+  constexpr int PW = 17;
+  double* P = lds;                  // panel rows J0..n-1: P[r * PW + c]
+  double* Ub = P + (size_t)n * PW;  // U12 columns: Ub[c * PW + t]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_zero = 0;
+
+  for (int J0 = 0; J0 < n; J0 += 16) {
+    const int jb = min(16, n - J0), rows = n - J0;
+    for (int idx = tid; idx < rows * 16; idx += NT) {
+      const int r = idx % rows, c = idx / rows;
+      P[r * PW + c] = c < jb ? S[(J0 + r) + (int64_t)(J0 + c) * n] : 0.0;
+    }
+    for (int r = tid; r < rows; r += NT) s_pl[r] = r;
+    __syncthreads();
+    if (wave == 0) {
+      for (int t = 0; t < jb; ++t) {
+        double best = -1.0;
+        int bi = 0x7fffffff;
+        for (int r = t + lane; r < rows; r += 64) {
+          const double v = fabs(P[r * PW + t]);
+          if (v > best) {
+            best = v;
+            bi = r;
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off);
+          const int oi = __shfl_xor(bi, off);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (bi == 0x7fffffff) bi = t;
+        if (lane == 0) {
+          ipiv[J0 + t] = J0 + bi;
+          const int a = s_pl[t];
+          s_pl[t] = s_pl[bi];
+          s_pl[bi] = a;
+        }
+        if (bi != t && lane < 16) {
+          const double a = P[t * PW + lane];
+          P[t * PW + lane] = P[bi * PW + lane];
+          P[bi * PW + lane] = a;
+        }
+        wave_lds_sync();
+        const double piv = P[t * PW + t];
+        if (piv == 0.0 && lane == 0) s_zero = 1;
+        const double rp = piv != 0.0 ? 1.0 / piv : 0.0;
+        for (int r = t + 1 + lane; r < rows; r += 64) P[r * PW + t] *= rp;
+        wave_lds_sync();
+        const int nr = rows - t - 1, nc = jb - t - 1;
+        for (int idx = lane; idx < nr * nc; idx += 64) {
+          const int r = t + 1 + idx % nr, c = t + 1 + idx / nr;
+          P[r * PW + c] -= P[r * PW + t] * P[t * PW + c];
+        }
+        wave_lds_sync();
+      }
+      // rows that moved in this panel (at most 2 jb): compact with a ballot
+      int base = 0;
+      for (int r0 = 0; r0 < rows; r0 += 64) {
+        const int r = r0 + lane;
+        const bool mv = r < rows && s_pl[r] != r;
+        const unsigned long long bal = __ballot(mv);
+        if (mv) {
+          const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+          s_mv[pos] = r;
+          s_mv[32 + pos] = s_pl[r];
+        }
+        base += __popcll(bal);
+      }
+      if (lane == 0) s_nmv = base;
+    }
+    __syncthreads();
+    // the panel back to S; interchanges on the other columns (only the rows
+    // that move, at most 32 per column)
+    for (int idx = tid; idx < rows * jb; idx += NT) {
+      const int r = idx % rows, c = idx / rows;
+      S[(J0 + r) + (int64_t)(J0 + c) * n] = P[r * PW + c];
+    }
+    const int nmv = s_nmv, nother = n - jb;
+    constexpr int MAXV = (32 * 256 + NT - 1) / NT;
+    double mv[MAXV];
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+      const int idx = tid + u * NT;
+      mv[u] = 0.0;
+      if (idx < nmv * nother) {
+        const int j = idx % nmv, co = idx / nmv;
+        const int c = co < J0 ? co : co + jb;
+        mv[u] = S[(J0 + s_mv[32 + j]) + (int64_t)c * n];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < nmv * nother) {
+        const int j = idx % nmv, co = idx / nmv;
+        const int c = co < J0 ? co : co + jb;
+        S[(J0 + s_mv[j]) + (int64_t)c * n] = mv[u];
+      }
+    }
+    __syncthreads();
+    // U12 = L11^{-1} A12 (columns right of the panel), kept in LDS too
+    const int ncr = n - J0 - jb;
+    for (int cc = tid; cc < ncr; cc += NT) {
+      const int c = J0 + jb + cc;
+      double x[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) x[t] = t < jb ? S[(J0 + t) + (int64_t)c * n] : 0.0;
+#pragma unroll
+      for (int t = 1; t < 16; ++t) {
+        double sacc = x[t];
+#pragma unroll
+        for (int q = 0; q < t; ++q) sacc -= P[t * PW + q] * x[q];
+        x[t] = sacc;
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        if (t < jb) S[(J0 + t) + (int64_t)c * n] = x[t];
+        Ub[cc * PW + t] = t < jb ? x[t] : 0.0;
+      }
+    }
+    __syncthreads();
+    // trailing update A22 -= L21 U12 on 16 x 16 tiles
+    const int nrt = (rows - jb + 15) / 16, nct = (ncr + 15) / 16;
+    for (int tt = wave; tt < nrt * nct; tt += NT / 64) {
+      const int tr = tt % nrt, tc = tt / nrt;
+      const int cl = lane & 15, kq = lane >> 4;
+      Mq::v4 acc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = jb + tr * 16 + Mq::row(lane, q), c = tc * 16 + cl;
+        acc[q] = (r < rows && c < ncr) ? S[(J0 + r) + (int64_t)(J0 + jb + c) * n] : 0.0;
+      }
+#pragma unroll
+      for (int k4 = 0; k4 < 16; k4 += 4) {
+        const int ra = jb + tr * 16 + cl;
+        const double a = ra < rows ? -P[ra * PW + k4 + kq] : 0.0;
+        const int cb = tc * 16 + cl;
+        const double b = cb < ncr ? Ub[cb * PW + k4 + kq] : 0.0;
+        acc = Mq::mma(a, b, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = jb + tr * 16 + Mq::row(lane, q), c = tc * 16 + cl;
+        if (r < rows && c < ncr) S[(J0 + r) + (int64_t)(J0 + jb + c) * n] = acc[q];
+      }
+    }
+    __syncthreads();
+  }
+  // permutation: row i of P S is row perm[i] of S
+  int* perm = k.sperm + (int64_t)mi * n;
+  if (tid == 0) {
+    for (int i = 0; i < n; ++i) s_pl[i] = i;
+    for (int t = 0; t < n; ++t) {
+      const int r = ipiv[t];
+      const int a = s_pl[t];
+      s_pl[t] = s_pl[r];
+      s_pl[r] = a;
+    }
+    if (s_zero) atomicMin(&k.status->iface, (unsigned long long)(mi + 1));
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) perm[i] = s_pl[i];
+  const int nbs = (n + 15) / 16;
+  const DenseAcc<double> D{S, n, n - 1, n - 1, n, nullptr};
+  diag_inverses<double>(D, k.sdinv + (int64_t)mi * nbs * dinv_stride(), tid, NT);
+}
+
+// ------------------------------------------------------- beta, delta solves
+// LDS doubles of k_mtrsm<HT>.
+template <int HT>
+__host__ __device__ constexpr int mtrsm_lds_elems() {
+  return tile_lds_elems(HT);
+}
+
+// blockIdx.x = (merge * 2 + job) * ncg + cg; job 0: beta = S^{-1} V_t(R),
+// job 1: delta = S^{-1} Dm; columns [64 cg, 64 cg + 64).
+template <int HT>
+__global__ __launch_bounds__(NT) void k_mtrsm(KParams k, int mbeg, int ncg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  const int cg = blockIdx.x % ncg, rest = blockIdx.x / ncg;
+  const int job = rest % 2, mm = rest / 2;
+  const MergeDesc J = k.merges[mbeg + mm];
+  const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif;
+  const bool nv = J.b < k.p - 1, nw = J.a > 0;
+  if (job == 0 ? !nv : !nw) return;
+  const int ncol = job == 0 ? ku : kl;
+  const int c0 = 64 * cg;
+  if (c0 >= ncol) return;
+  const Tips tp{k.tips, kw, ku};
+  double* C = k.coef + (int64_t)mi * kw * kw;
+  double* X = job == 0 ? C + kl : C + kl + (int64_t)ku * kw;   // ld kw
+  const double* src = job == 0 ? tp.Vt(J.right) : k.qw + (int64_t)mi * kw * kw;
+  const int64_t lds_src = job == 0 ? kw : ku;
+  const int* perm = k.sperm + (int64_t)mi * ku;
+  const int cw = min(64, ncol - c0);
+  for (int idx = threadIdx.x; idx < ku * cw; idx += NT) {
+    const int i = idx % ku, c = c0 + idx / ku;
+    X[i + (int64_t)c * kw] = src[perm[i] + (int64_t)c * lds_src];
+  }
+  __syncthreads();
+  const DenseAcc<double> D{k.sfac + (int64_t)mi * ku * ku, ku, ku - 1, ku - 1, ku, nullptr};
+  const double* dv = k.sdinv + (int64_t)mi * ((ku + 15) / 16) * dinv_stride();
+  const TSrc s = tsrc(X, 1, 1, kw, 0, ku);
+  const TDst d = tdst(X, nullptr, 1, 1, kw, ku, ku, ku);
+  tile_sweep<double, HT, OP_L_FWD>(D, dv, s, d, c0, ncol, lds);
+  tile_sweep<double, HT, OP_U_BWD>(D, dv, s, d, c0, ncol, lds);
+}
+
+// ---------------------------------------------------------------- solves
+// C = alpha A B + beta C with few columns (N <= 8): one thread per entry.
+__device__ inline void wg_gemm_nr(int M, int N, int K, double alpha, GM A, GM B, double beta, double* C,
+                                  int64_t ldc) {
+  for (int idx = threadIdx.x; idx < M * N; idx += NT) {
+    const int i = idx % M, j = idx / M;
+    const double* ap = A.p + (int64_t)i * A.rs;
+    const double* bp = B.p + (int64_t)j * B.cs;
+    double a0 = 0.0, a1 = 0.0;
+    int kk = 0;
+    for (; kk + 1 < K; kk += 2) {
+      a0 += ap[(int64_t)kk * A.cs] * bp[(int64_t)kk * B.rs];
+      a1 += ap[(int64_t)(kk + 1) * A.cs] * bp[(int64_t)(kk + 1) * B.rs];
+    }
+    if (kk < K) a0 += ap[(int64_t)kk * A.cs] * bp[(int64_t)kk * B.rs];
+    double* c = C + i + (int64_t)j * ldc;
+    *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * (a0 + a1);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void mgemm_any(int M, int N, int K, double alpha, GM A, GM B, double beta, double* C,
+                                          int64_t ldc, double* lds) {
+  if (N <= 8) wg_gemm_nr(M, N, K, alpha, A, B, beta, C, ldc);
+  else wg_gemm(M, N, K, alpha, A, B, beta, C, ldc, lds);
+}
+
+// Bottom-up pass of the reduced solve at merge J (see k_merge_up), with
+// S^{-1} applied as U^{-1} L^{-1} P.
+template <int HT>
+__global__ __launch_bounds__(NT) void k_mup(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  if (solve_idle(k)) return;
+  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
+  const Tips tp{k.tips, kw, ku};
+  double* nvl = k.nodeval + (int64_t)J.left * kw * R;
+  double* nvr = k.nodeval + (int64_t)J.right * kw * R;
+  double* nvj = k.nodeval + (int64_t)(k.p + mi) * kw * R;
+  double* s = k.st + (int64_t)mi * kw * R;
+  double* t = s + kl;
+  double* tmp = k.mtmp + (int64_t)mi * kw * R;
+  const int* perm = k.sperm + (int64_t)mi * ku;
+  wg_copy(ku, nrhs, nvr, kw, t, kw);
+  wg_copy(kl, nrhs, nvl + ku, kw, s, kw);
+  __syncthreads();
+  mgemm_any(ku, nrhs, kl, -1.0, gm(tp.Wt(J.right), 1, kw), gm(s, 1, kw), 1.0, t, kw, lds);
+  for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
+    const int i = idx % ku, q = idx / ku;
+    tmp[i + (int64_t)q * kw] = t[perm[i] + (int64_t)q * kw];
+  }
+  __syncthreads();
+  const DenseAcc<double> D{k.sfac + (int64_t)mi * ku * ku, ku, ku - 1, ku - 1, ku, nullptr};
+  const double* dv = k.sdinv + (int64_t)mi * ((ku + 15) / 16) * dinv_stride();
+  leaf_sweep<double, HT, OP_L_FWD>(D, dv, tsrc(tmp, 1, 1, kw, 0, ku), tdst(tmp, nullptr, 1, 1, kw, ku, ku, ku), 0,
+                                   nrhs, lds);
+  leaf_sweep<double, HT, OP_U_BWD>(D, dv, tsrc(tmp, 1, 1, kw, 0, ku), tdst(t, nullptr, 1, 1, kw, ku, ku, ku), 0,
+                                   nrhs, lds);
+  __syncthreads();
+  mgemm_any(kl, nrhs, ku, -1.0, gm(tp.Vb(J.left), 1, kw), gm(t, 1, kw), 1.0, s, kw, lds);
+  if (J.a > 0) {
+    wg_copy(ku, nrhs, nvl, kw, nvj, kw);
+    __syncthreads();
+    mgemm_any(ku, nrhs, ku, -1.0, gm(tp.Vt(J.left), 1, kw), gm(t, 1, kw), 1.0, nvj, kw, lds);
+  }
+  if (J.b < k.p - 1) {
+    wg_copy(kl, nrhs, nvr + ku, kw, nvj + ku, kw);
+    __syncthreads();
+    mgemm_any(kl, nrhs, kl, -1.0, gm(tp.Wb(J.right), 1, kw), gm(s, 1, kw), 1.0, nvj + ku, kw, lds);
+  }
+}
+
+// Top-down pass: interface values of J from its children's (see k_merge_down).
+static __global__ __launch_bounds__(NT) void k_mdown(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  if (solve_idle(k)) return;
+  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
+  double* x = k.xint + (int64_t)mi * kw * R;
+  const double* C = k.coef + (int64_t)mi * kw * kw;
+  wg_copy(kw, nrhs, k.st + (int64_t)mi * kw * R, kw, x, kw);
+  __syncthreads();
+  if (J.b < k.p - 1)
+    mgemm_any(kw, nrhs, ku, -1.0, gm(C, 1, kw), gm(k.xint + (int64_t)J.b * kw * R + kl, 1, kw), 1.0, x, kw, lds);
+  if (J.a > 0)
+    mgemm_any(kw, nrhs, kl, -1.0, gm(C + (int64_t)ku * kw, 1, kw), gm(k.xint + (int64_t)(J.a - 1) * kw * R, 1, kw),
+              1.0, x, kw, lds);
+}
+
+// Transposed reduced solve, first pass (see k_merge_tup).
+static __global__ __launch_bounds__(NT) void k_mtup(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  if (solve_idle(k)) return;
+  const int d = mbeg + blockIdx.x;
+  const MergeDesc J = k.merges[d];
+  const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
+  double* x = k.xint + (int64_t)mi * kw * R;
+  for (int ci = k.cptr[mi]; ci < k.cptr[mi + 1]; ++ci) {
+    const Contrib c = k.contrib[ci];
+    const double* cr = k.crl + (int64_t)c.merge * kw * R;
+    if (c.kind == 0) {
+      for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
+        const int r = idx % ku, q = idx / ku;
+        x[kl + r + (int64_t)q * kw] -= cr[r + (int64_t)q * kw];
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
+        const int r = idx % kl, q = idx / kl;
+        x[r + (int64_t)q * kw] -= cr[ku + r + (int64_t)q * kw];
+      }
+    }
+    __syncthreads();
+  }
+  wg_copy(kw, nrhs, x, kw, k.st + (int64_t)mi * kw * R, kw);
+  const double* C = k.coef + (int64_t)mi * kw * kw;
+  double* out = k.crl + (int64_t)d * kw * R;
+  if (J.b < k.p - 1) mgemm_any(ku, nrhs, kw, 1.0, gm(C, kw, 1), gm(x, 1, kw), 0.0, out, kw, lds);
+  if (J.a > 0) mgemm_any(kl, nrhs, kw, 1.0, gm(C + (int64_t)ku * kw, kw, 1), gm(x, 1, kw), 0.0, out + ku, kw, lds);
+}
+
+// Transposed reduced solve, second pass (see k_merge_tdown), with S^{-T}
+// applied as P^T L^{-T} U^{-T}.
+template <int HT>
+__global__ __launch_bounds__(NT) void k_mtdown(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  if (solve_idle(k)) return;
+  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
+  const Tips tp{k.tips, kw, ku};
+  double* sb = k.st + (int64_t)mi * kw * R;
+  double* tb = sb + kl;
+  double* nvl = k.nodeval + (int64_t)J.left * kw * R;
+  double* nvr = k.nodeval + (int64_t)J.right * kw * R;
+  double* nvj = k.nodeval + (int64_t)(k.p + mi) * kw * R;
+  double* tmp = k.mtmp + (int64_t)mi * kw * R;
+  const int* perm = k.sperm + (int64_t)mi * ku;
+  if (J.a > 0) mgemm_any(ku, nrhs, ku, -1.0, gm(tp.Vt(J.left), kw, 1), gm(nvj, 1, kw), 1.0, tb, kw, lds);
+  if (J.b < k.p - 1)
+    mgemm_any(kl, nrhs, kl, -1.0, gm(tp.Wb(J.right), kw, 1), gm(nvj + ku, 1, kw), 1.0, sb, kw, lds);
+  mgemm_any(ku, nrhs, kl, -1.0, gm(tp.Vb(J.left), kw, 1), gm(sb, 1, kw), 1.0, tb, kw, lds);
+  const DenseAcc<double> D{k.sfac + (int64_t)mi * ku * ku, ku, ku - 1, ku - 1, ku, nullptr};
+  const double* dv = k.sdinv + (int64_t)mi * ((ku + 15) / 16) * dinv_stride();
+  leaf_sweep<double, HT, OP_UT_FWD>(D, dv, tsrc(tb, 1, 1, kw, 0, ku), tdst(tmp, nullptr, 1, 1, kw, ku, ku, ku), 0,
+                                    nrhs, lds);
+  leaf_sweep<double, HT, OP_LT_BWD>(D, dv, tsrc(tmp, 1, 1, kw, 0, ku), tdst(tmp, nullptr, 1, 1, kw, ku, ku, ku), 0,
+                                    nrhs, lds);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
+    const int i = idx % ku, q = idx / ku;
+    tb[perm[i] + (int64_t)q * kw] = tmp[i + (int64_t)q * kw];
+  }
+  __syncthreads();
+  mgemm_any(kl, nrhs, ku, -1.0, gm(tp.Wt(J.right), kw, 1), gm(tb, 1, kw), 1.0, sb, kw, lds);
+  wg_copy(kl, nrhs, sb, kw, nvl + ku, kw);
+  wg_copy(ku, nrhs, tb, kw, nvr, kw);
+  if (J.a > 0) wg_copy(ku, nrhs, nvj, kw, nvl, kw);
+  if (J.b < k.p - 1) wg_copy(kl, nrhs, nvj + ku, kw, nvr + ku, kw);
+}
+
+// ---------------------------------------------------------------- runners
+template <typename K>
+inline void allow_lds_m(K kernel, size_t lds) {
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int HT>
+int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
+  const int kmax = k.kmax;
+  const size_t g_lds = (size_t)mgemm_lds_elems(kmax) * 8;
+  const size_t lu_lds = (size_t)mlu_lds_elems(k.ku) * 8;
+  const size_t tr_lds = (size_t)mtrsm_lds_elems<HT>() * 8 + 2048;
+  allow_lds_m(k_mgemm<1>, g_lds);
+  allow_lds_m(k_mgemm<4>, g_lds);
+  allow_lds_m(k_mgemm<5>, g_lds);
+  allow_lds_m(k_mlu, lu_lds);
+  allow_lds_m(k_mtrsm<HT>, tr_lds);
+  const int tpj = ((kmax + 31) / 32) * ((kmax + 31) / 32);
+  const int ncg = (kmax + 63) / 64;
+  for (int l = 0; l + 1 < (int)c.level_off.size(); ++l) {
+    const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
+    if (cnt <= 0) continue;
+    {
+      ProfScope ps("k_mgemm", st);
+      hipLaunchKernelGGL((k_mgemm<1>), dim3(cnt * mgemm_jobs(1) * tpj), dim3(NT), g_lds, st, k, beg, tpj);
+      SPIKE_CHECK_LAUNCH();
+    }
+    {
+      ProfScope ps("k_mlu", st);
+      hipLaunchKernelGGL(k_mlu, dim3(cnt), dim3(NT), lu_lds, st, k, beg);
+      SPIKE_CHECK_LAUNCH();
+    }
+    {
+      ProfScope ps("k_mtrsm", st);
+      hipLaunchKernelGGL((k_mtrsm<HT>), dim3(cnt * 2 * ncg), dim3(NT), tr_lds, st, k, beg, ncg);
+      SPIKE_CHECK_LAUNCH();
+    }
+    {
+      ProfScope ps("k_mgemm", st);
+      hipLaunchKernelGGL((k_mgemm<4>), dim3(cnt * mgemm_jobs(4) * tpj), dim3(NT), g_lds, st, k, beg, tpj);
+      SPIKE_CHECK_LAUNCH();
+    }
+    {
+      ProfScope ps("k_mgemm", st);
+      hipLaunchKernelGGL((k_mgemm<5>), dim3(cnt * mgemm_jobs(5) * tpj), dim3(NT), g_lds, st, k, beg, tpj);
+      SPIKE_CHECK_LAUNCH();
+    }
+  }
+  return 0;
+}
+
+template <int HT>
+int run_msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, bool trans) {
+  const size_t lds = (size_t)(tile_lds_elems(HT) > 2 * 16 * 65 ? tile_lds_elems(HT) : 2 * 16 * 65) * 8 + 2048;
+  allow_lds_m(k_mup<HT>, lds);
+  allow_lds_m(k_mtdown<HT>, lds);
+  allow_lds_m(k_mdown, lds);
+  allow_lds_m(k_mtup, lds);
+  const int L = (int)c.level_off.size() - 1;
+  if (!trans) {
+    for (int l = 0; l < L; ++l) {
+      const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
+      ProfScope ps("k_mup", st);
+      hipLaunchKernelGGL((k_mup<HT>), dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      SPIKE_CHECK_LAUNCH();
+    }
+    for (int l = L - 1; l >= 0; --l) {
+      const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
+      ProfScope ps("k_mdown", st);
+      hipLaunchKernelGGL(k_mdown, dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      SPIKE_CHECK_LAUNCH();
+    }
+  } else {
+    for (int l = 0; l < L; ++l) {
+      const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
+      ProfScope ps("k_mtup", st);
+      hipLaunchKernelGGL(k_mtup, dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      SPIKE_CHECK_LAUNCH();
+    }
+    for (int l = L - 1; l >= 0; --l) {
+      const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
+      ProfScope ps("k_mtdown", st);
+      hipLaunchKernelGGL((k_mtdown<HT>), dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      SPIKE_CHECK_LAUNCH();
+    }
+  }
+  return 0;
+}
+
+}  // namespace spike

@@ -130,6 +130,13 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
     if (pl.fast_lds > 160 * 1024) pl.fast = false;
   }
   if (pl.leaf_lds > 160 * 1024 || pl.merge_lds > 160 * 1024) return -4;
+  // reduced system on MFMA tiles: S (order ku) swept with a window that
+  // covers all of its 16-row blocks
+  pl.mfast = false;
+  if (pl.kmax <= 256) {
+    for (int h : {1, 2, 4, 8, 10, 16})
+      if (16 * h >= std::max(1, ku)) { pl.mht = h; pl.mfast = true; break; }
+  }
 
   // The last block is stored reversed (bandwidths swapped), so with pivoting
   // the storage must hold max(kl, ku) + kl + ku + 1 rows for either frame.
@@ -239,6 +246,9 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
   pl.off_ztip = take(8 * (size_t)nif * kw * R);
   pl.off_crl = take(8 * (size_t)std::max<size_t>(1, pl.merges.size()) * kw * R);
   pl.off_sscr = take(8 * (size_t)sscr);
+  pl.off_sdinv = take(8 * ((size_t)nif * ((ku + 15) / 16) * 512 + 512));
+  pl.off_sperm = take(sizeof(int) * (size_t)nif * std::max(1, ku));
+  pl.off_mtmp = take(8 * (size_t)nif * kw * R);
   if (pl.refine_enabled()) {
     pl.off_xacc = take(8 * (size_t)n * R);
     pl.off_res = take(8 * (size_t)n * R);

@@ -32,6 +32,8 @@ struct Plan {
   bool fast = false;    // MFMA tile engine for the full sweeps (non-pivoting)
   int ht = 0;           // its window height in 16-row tiles
   size_t fast_lds = 0;
+  bool mfast = false;   // reduced system on MFMA tiles (bandwidths up to 256)
+  int mht = 0;          // window height (16-row tiles) for sweeps with S's factors
 
   std::vector<LeafDesc> leaves;
   std::vector<MergeDesc> merges;   // grouped by level, level 1 first
@@ -48,6 +50,7 @@ struct Plan {
   size_t off_fscr = 0;
   size_t off_nodeval = 0, off_st = 0, off_xint = 0, off_ztip = 0, off_crl = 0;
   size_t off_sscr = 0, off_xacc = 0, off_res = 0, off_colred = 0;
+  size_t off_sdinv = 0, off_sperm = 0, off_mtmp = 0;
   size_t total = 0;
   size_t sscr_rows = 0;            // rows of solve scratch per leaf (max)
 

@@ -235,8 +235,8 @@ __device__ void tile_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
 // (non-pivoting factors), one thread per (block, column, factor): column t
 // of D^{-1} by substitution.  Blocks extending beyond the order are padded
 // with the identity.
-template <typename T>
-__device__ void diag_inverses(const BandAcc<T>& A, T* dinv, int gtid, int gstride) {
+template <typename T, typename Acc>
+__device__ void diag_inverses(const Acc& A, T* dinv, int gtid, int gstride) {
   const int m = A.m, nb = (m + 15) / 16;
   for (int w = gtid; w < nb * 32; w += gstride) {
     const int b = w >> 5, t = w & 15;
