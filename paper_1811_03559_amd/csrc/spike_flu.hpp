@@ -43,39 +43,16 @@ struct PivStats {
   int first_zero;
 };
 
-// An opaque copy of x: values derived from it are recomputed where they are
-// used instead of being hoisted out of the elimination loop and kept live.
-__device__ __forceinline__ int opaque(int x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-
-// Orders one wavefront's LDS accesses across lanes: stores before it are
-// visible to loads after it (a wavefront's LDS operations execute in order;
-// the fences keep the compiler from moving accesses across the point).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // LU (no interchanges) of one 16 x 16 tile held by one wavefront in the
 // accumulator layout, with the inverses of its unit-lower and upper factors.
 // a: in A, out L\U; xl: L^{-1}; xu: U^{-1} (same layout).  Rows at or beyond
-// `mrem` are padding (identity) and are left out of the statistics.
-// Pivot rows and columns are exchanged through `x` (16 * 17 + 48 elements of
-// LDS used by this wavefront only), with a wavefront-level sync between the
-// stores of a step and the loads that read them.
+// `mrem` are padding (identity) and are left out of the statistics.  Pivot
+// rows and columns move between lanes by cross-lane shuffles.
 template <typename T>
 __device__ __forceinline__ void lu_inv16(typename Mf<T>::v4& a, typename Mf<T>::v4& xl, typename Mf<T>::v4& xu,
-                                         T boost, int row0, int mrem, PivStats<T>& st, T* x) {
+                                         T boost, int row0, int mrem, PivStats<T>& st) {
   using M = Mf<T>;
-  constexpr int PADW = tile_pad();
-  const int lane = opaque(threadIdx.x & 63), cl = lane & 15, g = lane >> 4;
-  T* xrow = x;                 // row t of the working tile
-  T* xcol = x + 16 * PADW;     // column t of the working tile
-  T* xlr = xcol + 16;          // row t of L^{-1}
-  T* xuc = xlr + 16;           // column t of U^{-1}
+  const int lane = opaque(threadIdx.x & 63), cl = lane & 15, g = lane >> 4, gbase = lane & 48;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = M::row(lane, q);
@@ -85,18 +62,9 @@ __device__ __forceinline__ void lu_inv16(typename Mf<T>::v4& a, typename Mf<T>::
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int tg = M::grp(t), tq = M::reg(t);
-    if (g == tg) {
-      xrow[t * PADW + cl] = a[tq];
-      xlr[cl] = xl[tq];
-    }
-    if (cl == t) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xcol[M::row(lane, q)] = a[q];
-    }
-    wave_lds_sync();
-    T urow = xrow[t * PADW + cl];   // U(t, cl): row t is final
-    T piv = xrow[t * PADW + t];
-    const T xlt = xlr[cl];          // row t of L^{-1} is final
+    T urow = __shfl(a[tq], tg * 16 + cl);   // U(t, cl): row t is final
+    const T xlt = __shfl(xl[tq], tg * 16 + cl);   // row t of L^{-1} is final
+    T piv = lane_read(a[tq], tg * 16 + t);
     if (t < mrem) {
       if (boost > T(0) && fabs(piv) < boost) {
         piv = piv >= T(0) ? piv + boost : piv - boost;
@@ -110,17 +78,13 @@ __device__ __forceinline__ void lu_inv16(typename Mf<T>::v4& a, typename Mf<T>::
     const T rp = piv != T(0) ? T(1) / piv : T(0);
     if (cl == t) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        xu[q] *= rp;                           // column t of U^{-1}
-        xuc[M::row(lane, q)] = xu[q];
-      }
+      for (int q = 0; q < 4; ++q) xu[q] *= rp;   // column t of U^{-1}
     }
-    wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = M::row(lane, q);
-      const T lt = xcol[r];    // A(r, t)
-      const T xut = xuc[r];    // U^{-1}(r, t)
+      const T lt = __shfl(a[q], gbase + t);     // A(r, t)
+      const T xut = __shfl(xu[q], gbase + t);   // U^{-1}(r, t)
       if (r > t) {
         const T l = lt * rp;
         if (cl == t) a[q] = l;
@@ -129,7 +93,6 @@ __device__ __forceinline__ void lu_inv16(typename Mf<T>::v4& a, typename Mf<T>::
       }
       if (cl > t) xu[q] -= xut * urow;
     }
-    wave_lds_sync();   // this step's loads before the next step's stores
   }
 }
 
@@ -143,7 +106,6 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
   constexpr int PADW = tile_pad();
   constexpr int TS = 16 * PADW;          // one tile in LDS
   constexpr int BUF = (HT + 2) * TS;     // L^{-1}, U^{-1}, raw panel tiles 1..HT
-  T* xlu = lds + 2 * BUF;                // exchange area of the diagonal-tile LU
   __shared__ double s_norm[NW];
   __shared__ double s_minp[NW];
   __shared__ int s_boost[NW], s_zero[NW];
@@ -240,7 +202,7 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
 #pragma unroll
       for (int i = 1; i <= HT; ++i) lds_put(Pn + (1 + i) * TS, acc[i]);
       v4 xl, xu;
-      lu_inv16<T>(acc[0], xl, xu, boost, 16 * jp, m - 16 * jp, st, xlu);
+      lu_inv16<T>(acc[0], xl, xu, boost, 16 * jp, m - 16 * jp, st);
       lds_put(Pn, xl);
       lds_put(Pn + TS, xu);
       store_band(jp, jp, acc[0]);
@@ -327,10 +289,10 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
   }
 }
 
-// LDS bytes of k_flu<T, HT>: two panel buffers and the diagonal-tile exchange.
+// LDS bytes of k_flu<T, HT>: two panel buffers.
 template <typename T, int HT>
 constexpr size_t flu_lds_bytes() {
-  return ((size_t)2 * (HT + 2) * 16 * tile_pad() + 16 * tile_pad() + 48) * sizeof(T);
+  return (size_t)2 * (HT + 2) * 16 * tile_pad() * sizeof(T);
 }
 
 template <typename T, int HT>

@@ -20,6 +20,26 @@
 
 namespace spike {
 
+// Element-wise copy idx -> (load(idx), store(idx, v)) for idx in [0, total),
+// NL loads in flight per thread before their stores (global memory latency
+// is paid once per batch, not once per element).
+template <int NL, typename LD, typename ST>
+__device__ __forceinline__ void batched_copy(int total, LD load, ST store) {
+  for (int base = threadIdx.x; base < total; base += NT * NL) {
+    double v[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int idx = base + u * NT;
+      v[u] = idx < total ? load(idx) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int idx = base + u * NT;
+      if (idx < total) store(idx, v[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- GEMM jobs
 struct GJob {
   int M, N, K, addI, on;
@@ -140,16 +160,20 @@ __global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj) {
   double* As = lds;              // As[i * pa + kk]
   double* Bs = lds + 32 * pa;    // Bs[kk * 33 + j]
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < 32 * Kp; idx += NT) {
-    const int i = idx % 32, kk = idx / 32;
-    const int gi = i0 + i;
-    As[i * pa + kk] = (gi < g.M && kk < g.K) ? g.A[(int64_t)gi * g.ars + (int64_t)kk * g.acs] : 0.0;
-  }
-  for (int idx = tid; idx < 32 * Kp; idx += NT) {
-    const int kk = idx % Kp, j = idx / Kp;
-    const int gj = j0 + j;
-    Bs[kk * 33 + j] = (gj < g.N && kk < g.K) ? g.B[(int64_t)kk * g.brs + (int64_t)gj * g.bcs] : 0.0;
-  }
+  batched_copy<20>(
+      32 * Kp,
+      [&](int idx) {
+        const int i = idx % 32, kk = idx / 32, gi = i0 + i;
+        return (gi < g.M && kk < g.K) ? g.A[(int64_t)gi * g.ars + (int64_t)kk * g.acs] : 0.0;
+      },
+      [&](int idx, double v) { As[(idx % 32) * pa + idx / 32] = v; });
+  batched_copy<20>(
+      32 * Kp,
+      [&](int idx) {
+        const int kk = idx % Kp, gj = j0 + idx / Kp;
+        return (gj < g.N && kk < g.K) ? g.B[(int64_t)kk * g.brs + (int64_t)gj * g.bcs] : 0.0;
+      },
+      [&](int idx, double v) { Bs[(idx % Kp) * 33 + idx / Kp] = v; });
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6, wi = wave & 1, wj = wave >> 1, cl = lane & 15, kq = lane >> 4;
   M::v4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -179,6 +203,7 @@ static __global__ __launch_bounds__(NT) void k_mlu(KParams k, int mbeg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
   __shared__ int s_pl[256];     // panel-local row permutation
+  __shared__ int s_perm[256];   // row permutation of the whole factorisation
   __shared__ int s_mv[64];      // rows that move: destination, then source
   __shared__ int s_nmv;
   __shared__ int s_zero;
@@ -191,13 +216,17 @@ static __global__ __launch_bounds__(NT) void k_mlu(KParams k, int mbeg) {
   double* Ub = P + (size_t)n * PW;  // U12 columns: Ub[c * PW + t]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_zero = 0;
+  for (int i = tid; i < n; i += NT) s_perm[i] = i;
 
   for (int J0 = 0; J0 < n; J0 += 16) {
     const int jb = min(16, n - J0), rows = n - J0;
-    for (int idx = tid; idx < rows * 16; idx += NT) {
-      const int r = idx % rows, c = idx / rows;
-      P[r * PW + c] = c < jb ? S[(J0 + r) + (int64_t)(J0 + c) * n] : 0.0;
-    }
+    batched_copy<16>(
+        rows * 16,
+        [&](int idx) {
+          const int r = idx % rows, c = idx / rows;
+          return c < jb ? S[(J0 + r) + (int64_t)(J0 + c) * n] : 0.0;
+        },
+        [&](int idx, double v) { P[(idx % rows) * PW + idx / rows] = v; });
     for (int r = tid; r < rows; r += NT) s_pl[r] = r;
     __syncthreads();
     if (wave == 0) {
@@ -223,9 +252,12 @@ static __global__ __launch_bounds__(NT) void k_mlu(KParams k, int mbeg) {
         if (bi == 0x7fffffff) bi = t;
         if (lane == 0) {
           ipiv[J0 + t] = J0 + bi;
-          const int a = s_pl[t];
+          int a = s_pl[t];
           s_pl[t] = s_pl[bi];
           s_pl[bi] = a;
+          a = s_perm[J0 + t];
+          s_perm[J0 + t] = s_perm[J0 + bi];
+          s_perm[J0 + bi] = a;
         }
         if (bi != t && lane < 16) {
           const double a = P[t * PW + lane];
@@ -238,10 +270,14 @@ static __global__ __launch_bounds__(NT) void k_mlu(KParams k, int mbeg) {
         const double rp = piv != 0.0 ? 1.0 / piv : 0.0;
         for (int r = t + 1 + lane; r < rows; r += 64) P[r * PW + t] *= rp;
         wave_lds_sync();
-        const int nr = rows - t - 1, nc = jb - t - 1;
-        for (int idx = lane; idx < nr * nc; idx += 64) {
-          const int r = t + 1 + idx % nr, c = t + 1 + idx / nr;
-          P[r * PW + c] -= P[r * PW + t] * P[t * PW + c];
+        double urow[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) urow[c] = P[t * PW + c];
+        for (int r = t + 1 + lane; r < rows; r += 64) {
+          const double l = P[r * PW + t];
+#pragma unroll
+          for (int c = 0; c < 16; ++c)
+            if (c > t && c < jb) P[r * PW + c] -= l * urow[c];
         }
         wave_lds_sync();
       }
@@ -314,45 +350,44 @@ static __global__ __launch_bounds__(NT) void k_mlu(KParams k, int mbeg) {
     __syncthreads();
     // trailing update A22 -= L21 U12 on 16 x 16 tiles
     const int nrt = (rows - jb + 15) / 16, nct = (ncr + 15) / 16;
-    for (int tt = wave; tt < nrt * nct; tt += NT / 64) {
-      const int tr = tt % nrt, tc = tt / nrt;
-      const int cl = lane & 15, kq = lane >> 4;
-      Mq::v4 acc;
+    constexpr int TB = 6;   // tiles per wavefront whose loads are in flight together
+    const int cl = lane & 15, kq = lane >> 4;
+    for (int t0 = wave * TB; t0 < nrt * nct; t0 += (NT / 64) * TB) {
+      Mq::v4 acc[TB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = jb + tr * 16 + Mq::row(lane, q), c = tc * 16 + cl;
-        acc[q] = (r < rows && c < ncr) ? S[(J0 + r) + (int64_t)(J0 + jb + c) * n] : 0.0;
+      for (int u = 0; u < TB; ++u) {
+        const int tt = t0 + u, tr = tt % nrt, tc = tt / nrt;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = jb + tr * 16 + Mq::row(lane, q), c = tc * 16 + cl;
+          acc[u][q] = (tt < nrt * nct && r < rows && c < ncr) ? S[(J0 + r) + (int64_t)(J0 + jb + c) * n] : 0.0;
+        }
       }
 #pragma unroll
-      for (int k4 = 0; k4 < 16; k4 += 4) {
-        const int ra = jb + tr * 16 + cl;
-        const double a = ra < rows ? -P[ra * PW + k4 + kq] : 0.0;
-        const int cb = tc * 16 + cl;
-        const double b = cb < ncr ? Ub[cb * PW + k4 + kq] : 0.0;
-        acc = Mq::mma(a, b, acc);
-      }
+      for (int u = 0; u < TB; ++u) {
+        const int tt = t0 + u, tr = tt % nrt, tc = tt / nrt;
+        if (tt >= nrt * nct) continue;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = jb + tr * 16 + Mq::row(lane, q), c = tc * 16 + cl;
-        if (r < rows && c < ncr) S[(J0 + r) + (int64_t)(J0 + jb + c) * n] = acc[q];
+        for (int k4 = 0; k4 < 16; k4 += 4) {
+          const int ra = jb + tr * 16 + cl;
+          const double a = ra < rows ? -P[ra * PW + k4 + kq] : 0.0;
+          const int cb = tc * 16 + cl;
+          const double b = cb < ncr ? Ub[cb * PW + k4 + kq] : 0.0;
+          acc[u] = Mq::mma(a, b, acc[u]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = jb + tr * 16 + Mq::row(lane, q), c = tc * 16 + cl;
+          if (r < rows && c < ncr) S[(J0 + r) + (int64_t)(J0 + jb + c) * n] = acc[u][q];
+        }
       }
     }
     __syncthreads();
   }
   // permutation: row i of P S is row perm[i] of S
   int* perm = k.sperm + (int64_t)mi * n;
-  if (tid == 0) {
-    for (int i = 0; i < n; ++i) s_pl[i] = i;
-    for (int t = 0; t < n; ++t) {
-      const int r = ipiv[t];
-      const int a = s_pl[t];
-      s_pl[t] = s_pl[r];
-      s_pl[r] = a;
-    }
-    if (s_zero) atomicMin(&k.status->iface, (unsigned long long)(mi + 1));
-  }
-  __syncthreads();
-  for (int i = tid; i < n; i += NT) perm[i] = s_pl[i];
+  if (tid == 0 && s_zero) atomicMin(&k.status->iface, (unsigned long long)(mi + 1));
+  for (int i = tid; i < n; i += NT) perm[i] = s_perm[i];
   const int nbs = (n + 15) / 16;
   const DenseAcc<double> D{S, n, n - 1, n - 1, n, nullptr};
   diag_inverses<double>(D, k.sdinv + (int64_t)mi * nbs * dinv_stride(), tid, NT);
@@ -387,10 +422,9 @@ __global__ __launch_bounds__(NT) void k_mtrsm(KParams k, int mbeg, int ncg) {
   const int64_t lds_src = job == 0 ? kw : ku;
   const int* perm = k.sperm + (int64_t)mi * ku;
   const int cw = min(64, ncol - c0);
-  for (int idx = threadIdx.x; idx < ku * cw; idx += NT) {
-    const int i = idx % ku, c = c0 + idx / ku;
-    X[i + (int64_t)c * kw] = src[perm[i] + (int64_t)c * lds_src];
-  }
+  batched_copy<20>(
+      ku * cw, [&](int idx) { return src[perm[idx % ku] + (int64_t)(c0 + idx / ku) * lds_src]; },
+      [&](int idx, double v) { X[idx % ku + (int64_t)(c0 + idx / ku) * kw] = v; });
   __syncthreads();
   const DenseAcc<double> D{k.sfac + (int64_t)mi * ku * ku, ku, ku - 1, ku - 1, ku, nullptr};
   const double* dv = k.sdinv + (int64_t)mi * ((ku + 15) / 16) * dinv_stride();
@@ -408,15 +442,16 @@ __device__ inline void wg_gemm_nr(int M, int N, int K, double alpha, GM A, GM B,
     const int i = idx % M, j = idx / M;
     const double* ap = A.p + (int64_t)i * A.rs;
     const double* bp = B.p + (int64_t)j * B.cs;
-    double a0 = 0.0, a1 = 0.0;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int kk = 0;
-    for (; kk + 1 < K; kk += 2) {
-      a0 += ap[(int64_t)kk * A.cs] * bp[(int64_t)kk * B.rs];
-      a1 += ap[(int64_t)(kk + 1) * A.cs] * bp[(int64_t)(kk + 1) * B.rs];
+    for (; kk + 7 < K; kk += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += ap[(int64_t)(kk + u) * A.cs] * bp[(int64_t)(kk + u) * B.rs];
     }
-    if (kk < K) a0 += ap[(int64_t)kk * A.cs] * bp[(int64_t)kk * B.rs];
+    for (; kk < K; ++kk) a[0] += ap[(int64_t)kk * A.cs] * bp[(int64_t)kk * B.rs];
+    const double sum = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     double* c = C + i + (int64_t)j * ldc;
-    *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * (a0 + a1);
+    *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * sum;
   }
   __syncthreads();
 }

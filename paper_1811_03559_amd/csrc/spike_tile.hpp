@@ -58,6 +58,22 @@ struct Mf<float> {
   __host__ __device__ static constexpr int reg(int t) { return t & 3; }
 };
 
+// An opaque copy of x: values derived from it are recomputed where they are
+// used instead of being hoisted out of the elimination loop and kept live.
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Orders one wavefront's LDS accesses across lanes: stores before it are
+// visible to loads after it (a wavefront's LDS operations execute in order;
+// the fences keep the compiler from moving accesses across the point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Uniform read of lane `src` (src uniform across the wavefront).
 template <typename T>
 __device__ __forceinline__ T lane_read(T v, int src) {
