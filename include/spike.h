@@ -181,6 +181,50 @@ SPIKE_API int spike_profile_report(spike_kernel_time *out, int cap, int *count);
  * stream work using it has completed). */
 SPIKE_API int spike_destroy(spike_handle h);
 
+/* Batched solve stage (a project addition around the paper's solve stage:
+ * the D stage, recursive reduced solve and retrieval, or their transposes).
+ * For s = 0 .. count-1 solves op(A_s) X_s = F_s in place, A_s being the
+ * factorisation held by hs[s], op = transpose when trans[s] != 0:
+ *   hs[s]    handles from spike_factor (distinct systems may have different
+ *            n, bandwidths, partitions and precision)
+ *   nrhs[s]  columns of dB[s] (>= 0); ldb[s] >= max(1, n_s)
+ *   dB[s]    device, column-major n_s x nrhs[s], overwritten with X_s.
+ * Systems that share the kernel configuration (precision, window heights,
+ * operation) run each phase of the solve as one launch over all their
+ * partitions (or all their merges of one tree level), up to 32 systems per
+ * launch; the others are solved one after another.  Results are bitwise those
+ * of spike_solve / spike_solve_transpose on each system alone.  Systems must
+ * not share workspaces or right-hand sides.  Asynchronous on `stream`.
+ * Errors: -1 hs NULL or an invalid handle, -2 nrhs NULL or negative, -3 dB
+ * NULL (or dB[s] NULL with work to do), -4 ldb NULL or too small, -5 trans
+ * NULL, -6 count < 0, -1000-hipError on launch errors. */
+SPIKE_API int spike_solve_batch(const spike_handle *hs, const int32_t *nrhs,
+                                double *const *dB, const int64_t *ldb,
+                                const int32_t *trans, int32_t count,
+                                hipStream_t stream);
+
+/* Solve stage captured once into a HIP graph and replayed (callers that
+ * repeat the same solve on the same buffers, e.g. inside a time loop).  The
+ * capture records exactly the launches of spike_solve_batch (or of one
+ * spike_solve / spike_solve_transpose) with the given arguments on `stream`
+ * (a non-null stream that is not already capturing); nothing runs during the
+ * capture.  spike_graph_launch replays it on any stream: it reads dB[s] as F
+ * and overwrites it with X, exactly like the eager call.  Handles with
+ * refinement enabled are rejected (-1).  The handles, workspaces and dB
+ * buffers must outlive the graph.  Errors as spike_solve_batch, plus -7 null
+ * stream, -8 out NULL, -1000-hipError from capture or instantiation. */
+typedef struct spike_graph_s *spike_graph;
+SPIKE_API int spike_graph_capture_batch(const spike_handle *hs,
+                                        const int32_t *nrhs, double *const *dB,
+                                        const int64_t *ldb, const int32_t *trans,
+                                        int32_t count, hipStream_t stream,
+                                        spike_graph *out);
+SPIKE_API int spike_graph_capture_solve(spike_handle h, int32_t nrhs, double *dB,
+                                        int64_t ldb, int32_t trans,
+                                        hipStream_t stream, spike_graph *out);
+SPIKE_API int spike_graph_launch(spike_graph g, hipStream_t stream);
+SPIKE_API int spike_graph_destroy(spike_graph g);
+
 #ifdef __cplusplus
 }
 #endif

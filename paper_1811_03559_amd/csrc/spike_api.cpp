@@ -2,7 +2,9 @@
 // and stream-ordered launches.  No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
+#include <vector>
 #include <new>
 
 #include "../../include/spike.h"
@@ -91,6 +93,7 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   k.fast_tips = (pl.fast && pl.p >= 3) ? 1 : 0;
   k.dinv = w + pl.off_dinv;
   k.lu_done = 0;
+  k.skip = nullptr;
   k.sdinv = at<double>(w, pl.off_sdinv);
   k.sperm = at<int>(w, pl.off_sperm);
   k.mtmp = at<double>(w, pl.off_mtmp);
@@ -139,6 +142,9 @@ int upload(spike_handle h, hipStream_t st) {
                                     sizeof(spike::Contrib) * pl.contrib.size(),
                                     hipMemcpyHostToDevice, st))))
     return e;
+  static_assert(sizeof(spike::KParams) <= spike::kKParamsBytes, "parameter block slot too small");
+  if ((e = check_hip(hipMemcpyAsync(w + pl.off_kp, &h->kp, sizeof(spike::KParams), hipMemcpyHostToDevice, st))))
+    return e;
   return 0;
 }
 
@@ -168,7 +174,141 @@ int solve_common(spike_handle h, int32_t nrhs, double* dB, int64_t ldb, hipStrea
   return 0;
 }
 
+// Solves that can share batched launches: non-refined, MFMA tile engine for
+// the partition sweeps, reduced system on MFMA tiles (when p > 1).
+bool batchable(spike_handle h, int32_t nrhs) {
+  const spike::LaunchCfg& c = h->cfg;
+  return !h->plan.refine_enabled() && c.fast && nrhs >= c.fast_min_nrhs && nrhs <= h->plan.nrhs_max &&
+         (h->plan.p == 1 || c.mfast) && h->plan.n > 0;
+}
+
+// One pass of the solve stage over up to kMaxBatch systems that share the
+// kernel instantiation (precision, window heights) and the operation.
+int batch_pass(spike_handle const* hs, const int* idx, int cnt, const int32_t* nrhs, double* const* dB,
+               const int64_t* ldb, bool trans, hipStream_t st) {
+  spike::BatchArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.nsys = cnt;
+  size_t lds = 0;
+  int maxL = 0;
+  const spike::LaunchCfg& c0 = hs[idx[0]]->cfg;
+  for (int s = 0; s < cnt; ++s) {
+    spike_handle h = hs[idx[s]];
+    ba.kp[s] = reinterpret_cast<const spike::KParams*>(h->ws + h->plan.off_kp);
+    ba.B[s] = dB[idx[s]];
+    ba.ldb[s] = ldb[idx[s]];
+    ba.nrhs[s] = nrhs[idx[s]];
+    if (h->cfg.fast_lds > lds) lds = h->cfg.fast_lds;
+    const int L = (int)h->cfg.level_off.size() - 1;
+    if (L > maxL) maxL = L;
+  }
+  auto leaf_items = [&](int minus) {
+    int tot = 0;
+    for (int s = 0; s < cnt; ++s) {
+      ba.off[s] = tot;
+      tot += hs[idx[s]]->plan.p - minus;
+    }
+    ba.off[cnt] = tot;
+    return tot;
+  };
+  auto level_items = [&](int l) {
+    int tot = 0;
+    for (int s = 0; s < cnt; ++s) {
+      const std::vector<int>& lo = hs[idx[s]]->cfg.level_off;
+      const int L = (int)lo.size() - 1;
+      ba.off[s] = tot;
+      ba.mbeg[s] = l < L ? lo[l] : 0;
+      tot += l < L ? lo[l + 1] - lo[l] : 0;
+    }
+    ba.off[cnt] = tot;
+    return tot;
+  };
+  int e;
+  const bool f32 = c0.fp32;
+  const int ht = c0.ht, mht = c0.mht;
+  if (!trans) {
+    if ((e = spike::launch_phase_batch(ba, f32, ht, lds, st, 0, leaf_items(0)))) return e;
+    for (int l = 0; l < maxL; ++l)
+      if ((e = spike::launch_mlevel_batch(ba, mht, st, level_items(l), false, true))) return e;
+    for (int l = maxL - 1; l >= 0; --l)
+      if ((e = spike::launch_mlevel_batch(ba, mht, st, level_items(l), false, false))) return e;
+    if ((e = spike::launch_phase_batch(ba, f32, ht, lds, st, 1, leaf_items(0)))) return e;
+  } else {
+    if ((e = spike::launch_phase_batch(ba, f32, ht, lds, st, 2, leaf_items(0)))) return e;
+    if ((e = spike::run_gform_batch(ba, st, leaf_items(1)))) return e;
+    for (int l = 0; l < maxL; ++l)
+      if ((e = spike::launch_mlevel_batch(ba, mht, st, level_items(l), true, true))) return e;
+    for (int l = maxL - 1; l >= 0; --l)
+      if ((e = spike::launch_mlevel_batch(ba, mht, st, level_items(l), true, false))) return e;
+    if ((e = spike::launch_phase_batch(ba, f32, ht, lds, st, 3, leaf_items(0)))) return e;
+  }
+  return 0;
+}
+
+int solve_batch(const spike_handle* hs, const int32_t* nrhs, double* const* dB, const int64_t* ldb,
+                const int32_t* trans, int32_t count, hipStream_t st) {
+  if (count < 0) return -6;
+  if (count == 0) return 0;
+  if (!hs) return -1;
+  if (!nrhs) return -2;
+  if (!dB) return -3;
+  if (!ldb) return -4;
+  if (!trans) return -5;
+  for (int i = 0; i < count; ++i) {
+    if (!valid(hs[i])) return -1;
+    if (nrhs[i] < 0) return -2;
+    const int64_t n = hs[i]->plan.n;
+    if (nrhs[i] > 0 && n > 0 && dB[i] == nullptr) return -3;
+    if (ldb[i] < (n > 1 ? n : 1)) return -4;
+  }
+  // group by kernel instantiation and operation; others run one by one
+  std::vector<int> rest;
+  std::vector<std::vector<int>> groups;
+  std::vector<uint64_t> keys;
+  for (int i = 0; i < count; ++i) {
+    if (nrhs[i] == 0 || hs[i]->plan.n == 0) continue;
+    if (!batchable(hs[i], nrhs[i])) {
+      rest.push_back(i);
+      continue;
+    }
+    const spike::LaunchCfg& c = hs[i]->cfg;
+    const uint64_t key = ((uint64_t)(trans[i] != 0) << 40) | ((uint64_t)c.fp32 << 32) |
+                         ((uint64_t)c.ht << 16) | (uint64_t)(c.mfast ? c.mht : 0);
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != key) ++g;
+    if (g == keys.size()) {
+      keys.push_back(key);
+      groups.emplace_back();
+    }
+    groups[g].push_back(i);
+  }
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const std::vector<int>& v = groups[g];
+    const bool tr = (keys[g] >> 40) & 1;
+    for (size_t b = 0; b < v.size(); b += spike::kMaxBatch) {
+      const int cnt = (int)std::min<size_t>(spike::kMaxBatch, v.size() - b);
+      const int e = batch_pass(hs, v.data() + b, cnt, nrhs, dB, ldb, tr, st);
+      if (e) return e;
+    }
+  }
+  for (int i : rest) {
+    const int e = solve_common(hs[i], nrhs[i], dB[i], ldb[i], st, trans[i] != 0);
+    if (e) return e;
+  }
+  return 0;
+}
+
 }  // namespace
+
+struct spike_graph_s {
+  uint32_t magic;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace {
+constexpr uint32_t kGraphMagic = 0x6a2f1bu;
+}
 
 extern "C" {
 
@@ -258,6 +398,64 @@ int spike_handle_plan(spike_handle h, spike_plan_info* out) {
   if (!valid(h)) return -1;
   if (!out) return -2;
   to_info(h->plan, out);
+  return 0;
+}
+
+int spike_solve_batch(const spike_handle* hs, const int32_t* nrhs, double* const* dB, const int64_t* ldb,
+                      const int32_t* trans, int32_t count, hipStream_t stream) {
+  return solve_batch(hs, nrhs, dB, ldb, trans, count, stream);
+}
+
+int spike_graph_capture_batch(const spike_handle* hs, const int32_t* nrhs, double* const* dB,
+                              const int64_t* ldb, const int32_t* trans, int32_t count, hipStream_t stream,
+                              spike_graph* out) {
+  if (!out) return -8;
+  if (stream == nullptr) return -7;
+  for (int i = 0; i < count && hs; ++i)
+    if (valid(hs[i]) && hs[i]->plan.refine_enabled()) return -1;
+  spike_graph g = new (std::nothrow) spike_graph_s();
+  if (!g) return SPIKE_ERR_HIP - (int)hipErrorOutOfMemory;
+  int e = check_hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  if (e) {
+    delete g;
+    return e;
+  }
+  const int r = solve_batch(hs, nrhs, dB, ldb, trans, count, stream);
+  hipGraph_t graph = nullptr;
+  e = check_hip(hipStreamEndCapture(stream, &graph));
+  if (r || e) {
+    if (graph) (void)hipGraphDestroy(graph);
+    delete g;
+    return r ? r : e;
+  }
+  e = check_hip(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+  if (e) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return e;
+  }
+  g->graph = graph;
+  g->magic = kGraphMagic;
+  *out = g;
+  return 0;
+}
+
+int spike_graph_capture_solve(spike_handle h, int32_t nrhs, double* dB, int64_t ldb, int32_t trans,
+                              hipStream_t stream, spike_graph* out) {
+  return spike_graph_capture_batch(&h, &nrhs, &dB, &ldb, &trans, 1, stream, out);
+}
+
+int spike_graph_launch(spike_graph g, hipStream_t stream) {
+  if (!g || g->magic != kGraphMagic) return -1;
+  return check_hip(hipGraphLaunch(g->exec, stream));
+}
+
+int spike_graph_destroy(spike_graph g) {
+  if (!g || g->magic != kGraphMagic) return -1;
+  g->magic = 0;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
   return 0;
 }
 

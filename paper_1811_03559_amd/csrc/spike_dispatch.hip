@@ -102,6 +102,36 @@ int merge_solve(int nbd, const KParams& k, const LaunchCfg& c, hipStream_t st, i
 
 int launch_init_status(DevStatus* s, hipStream_t st) { return run_init_status(s, st); }
 
+namespace {
+template <typename T>
+int phase_batch(const BatchArgs& ba, int ht, size_t lds, hipStream_t st, int phase, int nitems) {
+  switch (ht) {
+    case 1: return run_fast_phase_batch<T, 1>(ba, lds, st, phase, nitems);
+    case 2: return run_fast_phase_batch<T, 2>(ba, lds, st, phase, nitems);
+    case 4: return run_fast_phase_batch<T, 4>(ba, lds, st, phase, nitems);
+    case 8: return run_fast_phase_batch<T, 8>(ba, lds, st, phase, nitems);
+    case 10: return run_fast_phase_batch<T, 10>(ba, lds, st, phase, nitems);
+    default: return run_fast_phase_batch<T, 16>(ba, lds, st, phase, nitems);
+  }
+}
+}  // namespace
+
+int launch_phase_batch(const BatchArgs& ba, bool fp32, int ht, size_t lds, hipStream_t st, int phase, int nitems) {
+  return fp32 ? phase_batch<float>(ba, ht, lds, st, phase, nitems)
+              : phase_batch<double>(ba, ht, lds, st, phase, nitems);
+}
+
+int launch_mlevel_batch(const BatchArgs& ba, int mht, hipStream_t st, int nitems, bool trans, bool up) {
+  switch (mht) {
+    case 1: return run_msolve_level_batch<1>(ba, st, nitems, trans, up);
+    case 2: return run_msolve_level_batch<2>(ba, st, nitems, trans, up);
+    case 4: return run_msolve_level_batch<4>(ba, st, nitems, trans, up);
+    case 8: return run_msolve_level_batch<8>(ba, st, nitems, trans, up);
+    case 10: return run_msolve_level_batch<10>(ba, st, nitems, trans, up);
+    default: return run_msolve_level_batch<16>(ba, st, nitems, trans, up);
+  }
+}
+
 int launch_factor(const KParams& k0, const LaunchCfg& c, hipStream_t st) {
   KParams k = k0;
   int e;

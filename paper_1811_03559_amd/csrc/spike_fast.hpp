@@ -110,11 +110,8 @@ __global__ __launch_bounds__(NT) void k_ftip_u(KParams k, int ncg) {
 
 // ---------------------------------------------------------------- solve stage
 template <typename T, int HT>
-__global__ __launch_bounds__(NT) void k_fdstage(KParams k, double* B, int64_t ldb, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
+__device__ void fdstage_body(const KParams& k, int li, double* B, int64_t ldb, int nrhs, T* lds) {
   if (solve_idle(k)) return;
-  const int li = blockIdx.x;
   const LeafDesc L = k.leaves[li];
   const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw;
   BandAcc<T> A = leaf_band<T>(k, L);
@@ -148,11 +145,8 @@ __global__ __launch_bounds__(NT) void k_fdstage(KParams k, double* B, int64_t ld
 }
 
 template <typename T, int HT>
-__global__ __launch_bounds__(NT) void k_fretrieve(KParams k, double* B, int64_t ldb, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
+__device__ void fretrieve_body(const KParams& k, int li, double* B, int64_t ldb, int nrhs, T* lds) {
   if (solve_idle(k)) return;
-  const int li = blockIdx.x;
   const LeafDesc L = k.leaves[li];
   if (L.type == LEAF_SINGLE) return;
   const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw, R = k.R;
@@ -201,11 +195,8 @@ __global__ __launch_bounds__(NT) void k_fretrieve(KParams k, double* B, int64_t 
 }
 
 template <typename T, int HT>
-__global__ __launch_bounds__(NT) void k_fzsweep(KParams k, double* B, int64_t ldb, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
+__device__ void fzsweep_body(const KParams& k, int li, double* B, int64_t ldb, int nrhs, T* lds) {
   if (solve_idle(k)) return;
-  const int li = blockIdx.x;
   const LeafDesc L = k.leaves[li];
   const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw, R = k.R;
   BandAcc<T> A = leaf_band<T>(k, L);
@@ -256,11 +247,8 @@ __global__ __launch_bounds__(NT) void k_fzsweep(KParams k, double* B, int64_t ld
 }
 
 template <typename T, int HT>
-__global__ __launch_bounds__(NT) void k_fdtstage(KParams k, double* B, int64_t ldb, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
+__device__ void fdtstage_body(const KParams& k, int li, double* B, int64_t ldb, int nrhs, T* lds) {
   if (solve_idle(k)) return;
-  const int li = blockIdx.x;
   const LeafDesc L = k.leaves[li];
   if (L.type == LEAF_SINGLE) return;
   const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw, R = k.R;
@@ -308,6 +296,55 @@ __global__ __launch_bounds__(NT) void k_fdtstage(KParams k, double* B, int64_t l
 template <typename K>
 inline void allow_lds_f(K kernel, size_t lds) {
   hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// Single-system and batched launches of the solve-stage partition kernels.
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fdstage(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fdstage_body<T, HT>(k, blockIdx.x, B, ldb, nrhs, reinterpret_cast<T*>(smem_raw));
+}
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fdstage_b(BatchArgs ba) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int s = batch_sys(ba, blockIdx.x);
+  fdstage_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.B[s], ba.ldb[s], ba.nrhs[s], reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fretrieve(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fretrieve_body<T, HT>(k, blockIdx.x, B, ldb, nrhs, reinterpret_cast<T*>(smem_raw));
+}
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fretrieve_b(BatchArgs ba) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int s = batch_sys(ba, blockIdx.x);
+  fretrieve_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.B[s], ba.ldb[s], ba.nrhs[s], reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fzsweep(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fzsweep_body<T, HT>(k, blockIdx.x, B, ldb, nrhs, reinterpret_cast<T*>(smem_raw));
+}
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fzsweep_b(BatchArgs ba) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int s = batch_sys(ba, blockIdx.x);
+  fzsweep_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.B[s], ba.ldb[s], ba.nrhs[s], reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fdtstage(KParams k, double* B, int64_t ldb, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  fdtstage_body<T, HT>(k, blockIdx.x, B, ldb, nrhs, reinterpret_cast<T*>(smem_raw));
+}
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_fdtstage_b(BatchArgs ba) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int s = batch_sys(ba, blockIdx.x);
+  fdtstage_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.B[s], ba.ldb[s], ba.nrhs[s], reinterpret_cast<T*>(smem_raw));
 }
 
 template <typename T, int HT>
@@ -361,6 +398,39 @@ int run_fast_phase(const KParams& k, const LaunchCfg& c, hipStream_t st, double*
       allow_lds_f(k_fdtstage<T, HT>, c.fast_lds);
       ProfScope ps("k_fdtstage", st);
       hipLaunchKernelGGL((k_fdtstage<T, HT>), dim3(k.p), dim3(NT), c.fast_lds, st, k, B, ldb, nrhs);
+      break;
+    }
+  }
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T, int HT>
+int run_fast_phase_batch(const BatchArgs& ba, size_t lds, hipStream_t st, int phase, int nitems) {
+  if (nitems <= 0) return 0;
+  switch (phase) {
+    case 0: {
+      allow_lds_f(k_fdstage_b<T, HT>, lds);
+      ProfScope ps("k_fdstage", st);
+      hipLaunchKernelGGL((k_fdstage_b<T, HT>), dim3(nitems), dim3(NT), lds, st, ba);
+      break;
+    }
+    case 1: {
+      allow_lds_f(k_fretrieve_b<T, HT>, lds);
+      ProfScope ps("k_fretrieve", st);
+      hipLaunchKernelGGL((k_fretrieve_b<T, HT>), dim3(nitems), dim3(NT), lds, st, ba);
+      break;
+    }
+    case 2: {
+      allow_lds_f(k_fzsweep_b<T, HT>, lds);
+      ProfScope ps("k_fzsweep", st);
+      hipLaunchKernelGGL((k_fzsweep_b<T, HT>), dim3(nitems), dim3(NT), lds, st, ba);
+      break;
+    }
+    default: {
+      allow_lds_f(k_fdtstage_b<T, HT>, lds);
+      ProfScope ps("k_fdtstage", st);
+      hipLaunchKernelGGL((k_fdtstage_b<T, HT>), dim3(nitems), dim3(NT), lds, st, ba);
       break;
     }
   }

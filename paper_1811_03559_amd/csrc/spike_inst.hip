@@ -22,12 +22,22 @@ template int run_flu<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStr
 #endif
 template int run_fast_phase<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, double*, int64_t,
                                                 int, int);
+template int run_fast_phase_batch<SPIKE_T, SPIKE_HT>(const BatchArgs&, size_t, hipStream_t, int, int);
 #elif defined(SPIKE_INST_MFAST)
 template int run_mfactor<SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t);
 template int run_msolve<SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, int, bool);
+template int run_msolve_level_batch<SPIKE_HT>(const BatchArgs&, hipStream_t, int, bool, bool);
 #elif defined(SPIKE_INST_COMMON)
 int run_init_status(DevStatus* s, hipStream_t st) {
   hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, s);
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
+int run_gform_batch(const BatchArgs& ba, hipStream_t st, int nitems) {
+  if (nitems <= 0) return 0;
+  ProfScope ps("k_gform", st);
+  hipLaunchKernelGGL(k_gform_b, dim3(nitems), dim3(NT), 0, st, ba);
   SPIKE_CHECK_LAUNCH();
   return 0;
 }

@@ -570,9 +570,8 @@ __global__ __launch_bounds__(NT) void k_leaf_zsweep(KParams k, double* B, int64_
 // replaced by B^/C^ times A^{-T} solves):
 //   G_{i,b}   = F_{i,b}   - C^_{i+1}^T top_kl(Z_{i+1})
 //   G_{i+1,t} = F_{i+1,t} - B^_i^T     bottom_ku(Z_i)
-static __global__ __launch_bounds__(NT) void k_gform(KParams k, const double* B, int64_t ldb, int nrhs) {
+__device__ inline void gform_body(const KParams& k, int mi, const double* B, int64_t ldb, int nrhs) {
   if (solve_idle(k)) return;
-  const int mi = blockIdx.x;
   const int kl = k.kl, ku = k.ku, kw = k.kw, R = k.R;
   const LeafDesc Lm = k.leaves[mi], Lr = k.leaves[mi + 1];
   double* x = k.xint + (int64_t)mi * kw * R;
@@ -591,6 +590,13 @@ static __global__ __launch_bounds__(NT) void k_gform(KParams k, const double* B,
     for (int c = 0; c < ku; ++c) acc -= bh[c + (int64_t)r * ku] * z[kl + c + (int64_t)q * kw];
     x[kl + r + (int64_t)q * kw] = acc;
   }
+}
+static __global__ __launch_bounds__(NT) void k_gform(KParams k, const double* B, int64_t ldb, int nrhs) {
+  gform_body(k, blockIdx.x, B, ldb, nrhs);
+}
+static __global__ __launch_bounds__(NT) void k_gform_b(BatchArgs ba) {
+  const int s = batch_sys(ba, blockIdx.x);
+  gform_body(*ba.kp[s], blockIdx.x - ba.off[s], ba.B[s], ba.ldb[s], ba.nrhs[s]);
 }
 
 // Transposed reduced solve, first pass (adjoint of the top-down pass), run

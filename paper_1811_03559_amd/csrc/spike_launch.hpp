@@ -58,6 +58,26 @@ struct KParams {
   double* mtmp;          // reduced-solve scratch, kw x R per interface
 };
 
+// Work items of several systems in one launch (solve-stage batching).
+// System s owns the items [off[s], off[s+1]) of the launch; for a merge
+// phase its items are the merges mbeg[s], mbeg[s]+1, ... of one tree level.
+constexpr int kMaxBatch = 32;
+struct BatchArgs {
+  int nsys;
+  int off[kMaxBatch + 1];
+  int mbeg[kMaxBatch];
+  int nrhs[kMaxBatch];
+  int64_t ldb[kMaxBatch];
+  double* B[kMaxBatch];
+  const KParams* kp[kMaxBatch];   // device copies of the systems' parameters
+};
+
+__device__ __forceinline__ int batch_sys(const BatchArgs& ba, int item) {
+  int s = 0;
+  while (s + 1 < ba.nsys && item >= ba.off[s + 1]) ++s;
+  return s;
+}
+
 struct LaunchCfg {
   int nb, nb_dense;
   bool fp32;
@@ -77,6 +97,11 @@ template <int HT>
 int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st);
 template <int HT>
 int run_msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, bool trans);
+template <typename T, int HT>
+int run_fast_phase_batch(const BatchArgs& ba, size_t lds, hipStream_t st, int phase, int nitems);
+template <int HT>
+int run_msolve_level_batch(const BatchArgs& ba, hipStream_t st, int nitems, bool trans, bool up);
+int run_gform_batch(const BatchArgs& ba, hipStream_t st, int nitems);
 template <typename T, int HT>
 int run_flu(const KParams& k, const LaunchCfg& c, hipStream_t st);
 template <typename T, int HT>
@@ -99,6 +124,8 @@ int run_init_status(DevStatus* s, hipStream_t st);
 int run_gform(const KParams& k, hipStream_t st, const double* B, int64_t ldb, int nrhs);
 
 int launch_init_status(DevStatus* s, hipStream_t st);
+int launch_phase_batch(const BatchArgs& ba, bool fp32, int ht, size_t lds, hipStream_t st, int phase, int nitems);
+int launch_mlevel_batch(const BatchArgs& ba, int mht, hipStream_t st, int nitems, bool trans, bool up);
 int launch_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);
 int launch_solve(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
                  bool trans);

@@ -465,11 +465,9 @@ __device__ __forceinline__ void mgemm_any(int M, int N, int K, double alpha, GM 
 // Bottom-up pass of the reduced solve at merge J (see k_merge_up), with
 // S^{-1} applied as U^{-1} L^{-1} P.
 template <int HT>
-__global__ __launch_bounds__(NT) void k_mup(KParams k, int mbeg, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
+__device__ void mup_body(const KParams& k, int d, int nrhs, double* lds) {
   if (solve_idle(k)) return;
-  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
   const Tips tp{k.tips, kw, ku};
   double* nvl = k.nodeval + (int64_t)J.left * kw * R;
@@ -509,11 +507,9 @@ __global__ __launch_bounds__(NT) void k_mup(KParams k, int mbeg, int nrhs) {
 }
 
 // Top-down pass: interface values of J from its children's (see k_merge_down).
-static __global__ __launch_bounds__(NT) void k_mdown(KParams k, int mbeg, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
+__device__ inline void mdown_body(const KParams& k, int d, int nrhs, double* lds) {
   if (solve_idle(k)) return;
-  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
   double* x = k.xint + (int64_t)mi * kw * R;
   const double* C = k.coef + (int64_t)mi * kw * kw;
@@ -527,11 +523,8 @@ static __global__ __launch_bounds__(NT) void k_mdown(KParams k, int mbeg, int nr
 }
 
 // Transposed reduced solve, first pass (see k_merge_tup).
-static __global__ __launch_bounds__(NT) void k_mtup(KParams k, int mbeg, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
+__device__ inline void mtup_body(const KParams& k, int d, int nrhs, double* lds) {
   if (solve_idle(k)) return;
-  const int d = mbeg + blockIdx.x;
   const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
   double* x = k.xint + (int64_t)mi * kw * R;
@@ -561,11 +554,9 @@ static __global__ __launch_bounds__(NT) void k_mtup(KParams k, int mbeg, int nrh
 // Transposed reduced solve, second pass (see k_merge_tdown), with S^{-T}
 // applied as P^T L^{-T} U^{-T}.
 template <int HT>
-__global__ __launch_bounds__(NT) void k_mtdown(KParams k, int mbeg, int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
+__device__ void mtdown_body(const KParams& k, int d, int nrhs, double* lds) {
   if (solve_idle(k)) return;
-  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
   const Tips tp{k.tips, kw, ku};
   double* sb = k.st + (int64_t)mi * kw * R;
@@ -596,6 +587,39 @@ __global__ __launch_bounds__(NT) void k_mtdown(KParams k, int mbeg, int nrhs) {
   wg_copy(ku, nrhs, tb, kw, nvr, kw);
   if (J.a > 0) wg_copy(ku, nrhs, nvj, kw, nvl, kw);
   if (J.b < k.p - 1) wg_copy(kl, nrhs, nvj + ku, kw, nvr + ku, kw);
+}
+
+// Single-system (merges mbeg + blockIdx.x of one level) and batched launches
+// of the reduced-solve kernels.
+template <int HT>
+__global__ __launch_bounds__(NT) void k_mup(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  mup_body<HT>(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+}
+static __global__ __launch_bounds__(NT) void k_mdown(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  mdown_body(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+}
+static __global__ __launch_bounds__(NT) void k_mtup(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  mtup_body(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+}
+template <int HT>
+__global__ __launch_bounds__(NT) void k_mtdown(KParams k, int mbeg, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  mtdown_body<HT>(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+}
+template <int HT, int KIND>
+__global__ __launch_bounds__(NT) void k_msolve_b(BatchArgs ba) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  const int s = batch_sys(ba, blockIdx.x);
+  const KParams& k = *ba.kp[s];
+  const int d = ba.mbeg[s] + (blockIdx.x - ba.off[s]);
+  if (KIND == 0) mup_body<HT>(k, d, ba.nrhs[s], lds);
+  else if (KIND == 1) mdown_body(k, d, ba.nrhs[s], lds);
+  else if (KIND == 2) mtup_body(k, d, ba.nrhs[s], lds);
+  else mtdown_body<HT>(k, d, ba.nrhs[s], lds);
 }
 
 // ---------------------------------------------------------------- runners
@@ -684,6 +708,43 @@ int run_msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, b
       SPIKE_CHECK_LAUNCH();
     }
   }
+  return 0;
+}
+
+// One level of the reduced solve for a batch of systems (up: the first pass,
+// bottom-up; else the second pass, top-down).
+template <int HT>
+int run_msolve_level_batch(const BatchArgs& ba, hipStream_t st, int nitems, bool trans, bool up) {
+  if (nitems <= 0) return 0;
+  const size_t lds = (size_t)(tile_lds_elems(HT) > 2 * 16 * 65 ? tile_lds_elems(HT) : 2 * 16 * 65) * 8 + 2048;
+  const int kind = trans ? (up ? 2 : 3) : (up ? 0 : 1);
+  switch (kind) {
+    case 0: {
+      allow_lds_m(k_msolve_b<HT, 0>, lds);
+      ProfScope ps("k_mup", st);
+      hipLaunchKernelGGL((k_msolve_b<HT, 0>), dim3(nitems), dim3(NT), lds, st, ba);
+      break;
+    }
+    case 1: {
+      allow_lds_m(k_msolve_b<HT, 1>, lds);
+      ProfScope ps("k_mdown", st);
+      hipLaunchKernelGGL((k_msolve_b<HT, 1>), dim3(nitems), dim3(NT), lds, st, ba);
+      break;
+    }
+    case 2: {
+      allow_lds_m(k_msolve_b<HT, 2>, lds);
+      ProfScope ps("k_mtup", st);
+      hipLaunchKernelGGL((k_msolve_b<HT, 2>), dim3(nitems), dim3(NT), lds, st, ba);
+      break;
+    }
+    default: {
+      allow_lds_m(k_msolve_b<HT, 3>, lds);
+      ProfScope ps("k_mtdown", st);
+      hipLaunchKernelGGL((k_msolve_b<HT, 3>), dim3(nitems), dim3(NT), lds, st, ba);
+      break;
+    }
+  }
+  SPIKE_CHECK_LAUNCH();
   return 0;
 }
 

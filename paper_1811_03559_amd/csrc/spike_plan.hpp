@@ -51,12 +51,17 @@ struct Plan {
   size_t off_nodeval = 0, off_st = 0, off_xint = 0, off_ztip = 0, off_crl = 0;
   size_t off_sscr = 0, off_xacc = 0, off_res = 0, off_colred = 0;
   size_t off_sdinv = 0, off_sperm = 0, off_mtmp = 0;
+  size_t off_kp = 0;               // device copy of the kernel parameter block
   size_t total = 0;
   size_t sscr_rows = 0;            // rows of solve scratch per leaf (max)
 
   int64_t reduced_size() const { return (int64_t)kw * (p - 1); }
   bool refine_enabled() const { return max_refine > 0; }
 };
+
+// Bytes reserved in the workspace for the device copy of the kernel
+// parameter block (used by batched launches).
+constexpr size_t kKParamsBytes = 1024;
 
 // Fills the defaults documented in spike.h.
 void default_opts(spike_opts *o);

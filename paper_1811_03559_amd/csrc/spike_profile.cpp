@@ -49,6 +49,9 @@ void recycle_all() {
 bool prof_enabled() { return g_on.load(std::memory_order_relaxed); }
 
 int prof_begin(const char* name, hipStream_t st) {
+  // no timing events inside a stream capture (they would become graph nodes)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
   Rec r{name, take_event(), take_event()};
   if (!r.start || !r.end) return -1;

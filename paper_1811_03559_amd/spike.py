@@ -87,6 +87,18 @@ def lib():
             L.spike_handle_plan.argtypes = [_c_p, ctypes.POINTER(PlanInfo)]
             L.spike_destroy.restype = ctypes.c_int
             L.spike_destroy.argtypes = [_c_p]
+            L.spike_solve_batch.restype = ctypes.c_int
+            L.spike_solve_batch.argtypes = [_c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, _c_p]
+            L.spike_graph_capture_batch.restype = ctypes.c_int
+            L.spike_graph_capture_batch.argtypes = [_c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, _c_p,
+                                                    ctypes.POINTER(_c_p)]
+            L.spike_graph_capture_solve.restype = ctypes.c_int
+            L.spike_graph_capture_solve.argtypes = [_c_p, _c_i32, _c_p, _c_i64, _c_i32, _c_p,
+                                                    ctypes.POINTER(_c_p)]
+            L.spike_graph_launch.restype = ctypes.c_int
+            L.spike_graph_launch.argtypes = [_c_p, _c_p]
+            L.spike_graph_destroy.restype = ctypes.c_int
+            L.spike_graph_destroy.argtypes = [_c_p]
             L.spike_profile_enable.restype = ctypes.c_int
             L.spike_profile_enable.argtypes = [ctypes.c_int]
             L.spike_profile_report.restype = ctypes.c_int
@@ -243,3 +255,73 @@ class Factorization:
 
 def levels_for(p: int) -> int:
     return 0 if p <= 1 else math.ceil(math.log2(p))
+
+
+def _batch_arrays(facs, Bs, trans):
+    """ctypes arrays for the batched entry points (B tensors: (nrhs, n), C order)."""
+    cnt = len(facs)
+    if len(Bs) != cnt:
+        raise ValueError("one right-hand side per factorisation")
+    if isinstance(trans, bool):
+        trans = [trans] * cnt
+    hs = (_c_p * cnt)(*[f.h.value for f in facs])
+    nr = (_c_i32 * cnt)()
+    bp = (_c_p * cnt)()
+    ld = (_c_i64 * cnt)()
+    tr = (_c_i32 * cnt)(*[1 if t else 0 for t in trans])
+    for i, (f, B) in enumerate(zip(facs, Bs)):
+        if B.dim() == 1:
+            B = B.view(1, -1)
+        if B.shape[1] != f.n or B.stride(1) != 1:
+            raise ValueError("B must have shape (nrhs, n) with unit column stride")
+        nr[i] = int(B.shape[0])
+        bp[i] = B.data_ptr()
+        ld[i] = B.stride(0) if B.shape[0] > 1 else max(f.n, 1)
+    return cnt, hs, nr, bp, ld, tr
+
+
+def solve_batch(facs, Bs, trans=False, stream=None):
+    """In-place solves of several factorisations, phases batched across
+    systems (spike_solve_batch).  ``trans``: bool or one bool per system."""
+    cnt, hs, nr, bp, ld, tr = _batch_arrays(facs, Bs, trans)
+    rc = lib().spike_solve_batch(hs, nr, bp, ld, tr, cnt, _stream_handle(stream))
+    if rc != 0:
+        raise SpikeError("spike_solve_batch", rc)
+    return Bs
+
+
+class SolveGraph:
+    """The solve stage of one or more factorisations captured into a HIP
+    graph on ``stream`` (a torch.cuda.Stream other than the default), to be
+    replayed with launch()."""
+
+    def __init__(self, facs, Bs, trans=False, stream=None):
+        import torch
+        if not isinstance(facs, (list, tuple)):
+            facs, Bs = [facs], [Bs]
+        self.facs, self.Bs = list(facs), list(Bs)   # keep them alive with the graph
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        cnt, hs, nr, bp, ld, tr = _batch_arrays(self.facs, self.Bs, trans)
+        g = _c_p()
+        rc = lib().spike_graph_capture_batch(hs, nr, bp, ld, tr, cnt, ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(g))
+        if rc != 0:
+            raise SpikeError("spike_graph_capture_batch", rc)
+        self.g = g
+
+    def launch(self, stream=None):
+        rc = lib().spike_graph_launch(self.g, _stream_handle(stream))
+        if rc != 0:
+            raise SpikeError("spike_graph_launch", rc)
+
+    def close(self):
+        if getattr(self, "g", None) is not None and self.g.value:
+            lib().spike_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
