@@ -214,6 +214,40 @@ SPIKE_API int spike_solve_batch(const spike_handle *hs, const int32_t *nrhs,
  * buffers must outlive the graph.  Errors as spike_solve_batch, plus -7 null
  * stream, -8 out NULL, -1000-hipError from capture or instantiation. */
 typedef struct spike_graph_s *spike_graph;
+
+/* Autotuner (a project addition to the load-balancing section, whose machine
+ * constant K is measured here rather than assumed).  Times factorisation +
+ * solve of candidate plans on the caller's matrix and device: partition
+ * counts around the number of compute units and the planner's default, equal
+ * sizing; estimates K = (solve ms * max(kl,ku)) / (factor ms * nrhs) from the
+ * fastest one and times that p again with R13 sizing at that K.  Blocks the
+ * host until each timing is done.
+ *   dAB, ldab   the matrix (as spike_factor)
+ *   nrhs        columns of the solves to tune for (>= 1)
+ *   base        options to start from (NULL: defaults); p and sizing are
+ *               tuned, everything else is kept
+ *   dWork       workspace of work_bytes; candidates needing more are skipped
+ *               (spike_autotune_workspace_size gives the size that fits all)
+ *   dB, ldb     device n x nrhs scratch for the timed solves (overwritten)
+ *   out         best options and their timings, K, candidates timed.
+ * Errors: -1 n < 1, -2 kl < 0, -3 ku < 0, -4 dAB NULL, -5 ldab too small,
+ * -6 nrhs < 1, -8 dWork NULL, -9 no candidate fits, -10 dB NULL or ldb < n,
+ * -13 out NULL, or the error of a failing factor/solve. */
+typedef struct spike_tune_result {
+    spike_opts opts;
+    double factor_ms;
+    double solve_ms;
+    double K;
+    int32_t candidates;
+} spike_tune_result;
+
+SPIKE_API int spike_autotune_workspace_size(int64_t n, int32_t kl, int32_t ku,
+                                            const spike_opts *base, size_t *bytes);
+SPIKE_API int spike_autotune(int64_t n, int32_t kl, int32_t ku, const double *dAB,
+                             int64_t ldab, int32_t nrhs, const spike_opts *base,
+                             void *dWork, size_t work_bytes, double *dB,
+                             int64_t ldb, hipStream_t stream,
+                             spike_tune_result *out);
 SPIKE_API int spike_graph_capture_batch(const spike_handle *hs,
                                         const int32_t *nrhs, double *const *dB,
                                         const int64_t *ldb, const int32_t *trans,
@@ -224,6 +258,81 @@ SPIKE_API int spike_graph_capture_solve(spike_handle h, int32_t nrhs, double *dB
                                         hipStream_t stream, spike_graph *out);
 SPIKE_API int spike_graph_launch(spike_graph g, hipStream_t stream);
 SPIKE_API int spike_graph_destroy(spike_graph g);
+
+/* Serving runtime (a project addition: many requests of mixed n, bandwidth
+ * and nrhs on one GPU, reusing the paper's factor-once, solve-many structure
+ * (factorisation reused by the transpose solve, section "Transpose solve
+ * option") across requests).  The server owns one device allocation of
+ * hbm_budget bytes made at creation (its only allocation), carves
+ * factorisation workspaces out of it, keeps them resident per matrix id and
+ * evicts idle ones least-recently-used when a new matrix needs room.  A
+ * worker thread admits queued requests while request slots and pool memory
+ * are free (continuous batching: requests that arrive while others run are
+ * admitted as slots free up), orders all work on one matrix on that matrix's
+ * stream, and launches the admitted solves of one stream as one batched
+ * solve.  Results are bitwise those of factoring and solving each request
+ * alone with the same options.  Admission is first-come first-served when
+ * pool memory is short: a request waiting for room holds back the requests
+ * queued after it.  The server's streams do not wait for the caller's: dAB
+ * and dB must hold their data (synchronised) when a request is submitted,
+ * and dB must not be touched until the request is done.  The numerical
+ * status (info) is read once per factorisation with a synchronous copy. */
+typedef struct spike_server_s *spike_server;
+
+typedef struct spike_server_opts {
+    size_t hbm_budget;    /* device bytes for resident factorisations  [16 GiB] */
+    int32_t max_inflight; /* requests on the device at once              [64] */
+    int32_t streams;      /* device streams work is spread over (1..16)   [4] */
+    int32_t batch_window; /* solves fused into one batched launch        [32] */
+} spike_server_opts;
+
+typedef struct spike_request {
+    int64_t matrix_id;    /* caller's id of A: same id = same matrix, reuse   */
+    int64_t n;
+    int32_t kl, ku;
+    const double *dAB;    /* device band (spike_factor layout); must stay
+                             valid while the id may be (re)factored          */
+    int64_t ldab;
+    spike_opts opts;      /* factorisation options (first request of an id)  */
+    int32_t nrhs;         /* >= 1 */
+    double *dB;           /* device n x nrhs: F in, X out                    */
+    int64_t ldb;
+    int32_t trans;        /* != 0: solve A^T X = F                           */
+} spike_request;
+
+typedef struct spike_request_status {
+    int32_t state;        /* 0 queued, 1 on the device, 2 done, 3 failed     */
+    int32_t error;        /* failure code (-100: larger than the budget)     */
+    int64_t info;         /* spike_status.info of the factorisation          */
+    double latency_s;     /* submission to observed completion, -1 if open   */
+} spike_request_status;
+
+typedef struct spike_server_report {
+    int64_t completed, failed, factorizations, evictions, resident;
+    size_t hbm_used, hbm_high_water;
+    double p50_s, p99_s, max_s;   /* latency percentiles of completed requests */
+    double solves_per_s;          /* completed / (last completion - first submission) */
+} spike_server_report;
+
+SPIKE_API void spike_server_default_opts(spike_server_opts *opts);
+/* Errors: -1 bad options, -2 out NULL, -1000-hipError (allocation, streams). */
+SPIKE_API int spike_server_create(const spike_server_opts *opts, spike_server *out);
+/* Queue a request (non-blocking).  Errors: -1 bad server, -2 bad request,
+ * -3 ticket NULL. */
+SPIKE_API int spike_server_submit(spike_server s, const spike_request *req,
+                                  int64_t *ticket);
+/* Status without waiting / after waiting for completion.  -2 unknown ticket. */
+SPIKE_API int spike_server_poll(spike_server s, int64_t ticket,
+                                spike_request_status *st);
+SPIKE_API int spike_server_wait(spike_server s, int64_t ticket,
+                                spike_request_status *st);
+/* Forget a finished request (-3 if it is not finished). */
+SPIKE_API int spike_server_release(spike_server s, int64_t ticket);
+/* Wait until every queued request has finished. */
+SPIKE_API int spike_server_drain(spike_server s);
+SPIKE_API int spike_server_stats(spike_server s, spike_server_report *out);
+/* Finish queued work, release every factorisation and the pool. */
+SPIKE_API int spike_server_destroy(spike_server s);
 
 #ifdef __cplusplus
 }

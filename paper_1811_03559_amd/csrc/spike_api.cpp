@@ -300,6 +300,40 @@ int solve_batch(const spike_handle* hs, const int32_t* nrhs, double* const* dB, 
 
 }  // namespace
 
+namespace {
+
+// Candidate plans of the autotuner: partition counts around the device's
+// compute-unit count (and the planner's default), equal sizing; infeasible
+// ones (partitions shorter than kl + ku) are dropped.
+std::vector<spike_opts> tune_candidates(int64_t n, int32_t kl, int32_t ku, const spike_opts& base) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::vector<int> ps;
+  spike::Plan pl0;
+  spike_opts o0 = base;
+  o0.p = 0;
+  o0.sizing = 0;
+  if (spike::make_plan(n, kl, ku, o0, pl0) == 0) ps.push_back(pl0.p);
+  for (int f : {1, 2, 4}) ps.push_back(cus * f / 2);
+  ps.push_back(cus);
+  std::vector<spike_opts> out;
+  for (int p : ps) {
+    if (p < 1) continue;
+    bool dup = false;
+    for (auto& o : out) dup = dup || o.p == p;
+    if (dup) continue;
+    spike_opts o = base;
+    o.p = p;
+    o.sizing = 0;
+    spike::Plan pl;
+    if (spike::make_plan(n, kl, ku, o, pl) == 0) out.push_back(o);
+  }
+  return out;
+}
+
+}  // namespace
+
 struct spike_graph_s {
   uint32_t magic;
   hipGraph_t graph;
@@ -456,6 +490,120 @@ int spike_graph_destroy(spike_graph g) {
   (void)hipGraphExecDestroy(g->exec);
   (void)hipGraphDestroy(g->graph);
   delete g;
+  return 0;
+}
+
+int spike_autotune_workspace_size(int64_t n, int32_t kl, int32_t ku, const spike_opts* base, size_t* bytes) {
+  if (n < 1) return -1;
+  if (kl < 0) return -2;
+  if (ku < 0) return -3;
+  if (!bytes) return -5;
+  spike_opts b;
+  if (base) b = *base;
+  else spike::default_opts(&b);
+  size_t best = 0;
+  for (const spike_opts& o : tune_candidates(n, kl, ku, b)) {
+    spike::Plan pl;
+    if (spike::make_plan(n, kl, ku, o, pl) == 0) best = std::max(best, pl.total);
+    spike_opts r = o;
+    r.sizing = 1;
+    r.K = 4.0;
+    if (spike::make_plan(n, kl, ku, r, pl) == 0) best = std::max(best, pl.total);
+  }
+  *bytes = best;
+  return best ? 0 : -4;
+}
+
+int spike_autotune(int64_t n, int32_t kl, int32_t ku, const double* dAB, int64_t ldab, int32_t nrhs,
+                   const spike_opts* base, void* dWork, size_t work_bytes, double* dB, int64_t ldb,
+                   hipStream_t stream, spike_tune_result* out) {
+  if (n < 1) return -1;
+  if (kl < 0) return -2;
+  if (ku < 0) return -3;
+  if (!dAB) return -4;
+  if (ldab < (int64_t)kl + ku + 1) return -5;
+  if (nrhs < 1) return -6;
+  if (!dWork) return -8;
+  if (!dB || ldb < n) return -10;
+  if (!out) return -13;
+  spike_opts b;
+  if (base) b = *base;
+  else spike::default_opts(&b);
+  b.nrhs_hint = nrhs;
+  if (b.nrhs_max < nrhs) b.nrhs_max = nrhs;
+  hipEvent_t ev[3];
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return SPIKE_ERR_HIP - (int)hipErrorOutOfMemory;
+  auto run = [&](const spike_opts& o, double& tf, double& ts) -> int {
+    size_t need = 0;
+    if (spike_workspace_size(n, kl, ku, &o, &need) || need > work_bytes) return 1;
+    spike_handle h = nullptr;
+    (void)hipEventRecord(ev[0], stream);
+    int e = spike_factor(n, kl, ku, dAB, ldab, &o, dWork, work_bytes, stream, &h);
+    if (e) return e;
+    (void)hipEventRecord(ev[1], stream);
+    e = spike_solve(h, nrhs, dB, ldb, stream);
+    (void)hipEventRecord(ev[2], stream);
+    if (!e) e = check_hip(hipEventSynchronize(ev[2]));
+    float a = 0.f, c = 0.f;
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&c, ev[1], ev[2]);
+    tf = a;
+    ts = c;
+    spike_destroy(h);
+    return e;
+  };
+  double best = 1e300, bf = 0, bs = 0;
+  int ncand = 0, err = 0;
+  spike_opts bo = b;
+  for (const spike_opts& o : tune_candidates(n, kl, ku, b)) {
+    double tf = 0, ts = 0;
+    const int e = run(o, tf, ts);
+    if (e > 0) continue;          // does not fit the workspace
+    if (e < 0) {
+      err = e;
+      break;
+    }
+    ++ncand;
+    if (tf + ts < best) {
+      best = tf + ts;
+      bf = tf;
+      bs = ts;
+      bo = o;
+    }
+  }
+  double K = 0.0;
+  if (!err && ncand > 0) {
+    // machine constant of the load-balancing model: solve cost per row and
+    // column over factor cost per row, per unit of bandwidth
+    const double kk = std::max(1, std::max(kl, ku));
+    K = bf > 0 ? (bs * kk) / (bf * nrhs) : 0.0;
+    if (K > 0 && bo.p >= 3) {
+      spike_opts r = bo;
+      r.sizing = 1;
+      r.K = K;
+      double tf = 0, ts = 0;
+      const int e = run(r, tf, ts);
+      if (e < 0) err = e;
+      if (e == 0) {
+        ++ncand;
+        if (tf + ts < best) {
+          best = tf + ts;
+          bf = tf;
+          bs = ts;
+          bo = r;
+        }
+      }
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (err) return err;
+  if (ncand == 0) return -9;
+  out->opts = bo;
+  out->factor_ms = bf;
+  out->solve_ms = bs;
+  out->K = K;
+  out->candidates = ncand;
   return 0;
 }
 

@@ -48,6 +48,33 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("calls", _c_i32), ("total_ms", _c_dbl)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("opts", Opts), ("factor_ms", _c_dbl), ("solve_ms", _c_dbl), ("K", _c_dbl),
+                ("candidates", _c_i32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", _c_size), ("max_inflight", _c_i32), ("streams", _c_i32),
+                ("batch_window", _c_i32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("matrix_id", _c_i64), ("n", _c_i64), ("kl", _c_i32), ("ku", _c_i32), ("dAB", _c_p),
+                ("ldab", _c_i64), ("opts", Opts), ("nrhs", _c_i32), ("dB", _c_p), ("ldb", _c_i64),
+                ("trans", _c_i32)]
+
+
+class RequestStatus(ctypes.Structure):
+    _fields_ = [("state", _c_i32), ("error", _c_i32), ("info", _c_i64), ("latency_s", _c_dbl)]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [("completed", _c_i64), ("failed", _c_i64), ("factorizations", _c_i64),
+                ("evictions", _c_i64), ("resident", _c_i64), ("hbm_used", _c_size),
+                ("hbm_high_water", _c_size), ("p50_s", _c_dbl), ("p99_s", _c_dbl), ("max_s", _c_dbl),
+                ("solves_per_s", _c_dbl)]
+
+
 class SpikeError(RuntimeError):
     def __init__(self, fn, code):
         super().__init__("%s returned %d" % (fn, code))
@@ -99,6 +126,29 @@ def lib():
             L.spike_graph_launch.argtypes = [_c_p, _c_p]
             L.spike_graph_destroy.restype = ctypes.c_int
             L.spike_graph_destroy.argtypes = [_c_p]
+            L.spike_server_default_opts.restype = None
+            L.spike_server_default_opts.argtypes = [ctypes.POINTER(ServerOpts)]
+            L.spike_server_create.restype = ctypes.c_int
+            L.spike_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_c_p)]
+            L.spike_server_submit.restype = ctypes.c_int
+            L.spike_server_submit.argtypes = [_c_p, ctypes.POINTER(Request), ctypes.POINTER(_c_i64)]
+            for fn in ("spike_server_poll", "spike_server_wait"):
+                getattr(L, fn).restype = ctypes.c_int
+                getattr(L, fn).argtypes = [_c_p, _c_i64, ctypes.POINTER(RequestStatus)]
+            L.spike_server_release.restype = ctypes.c_int
+            L.spike_server_release.argtypes = [_c_p, _c_i64]
+            L.spike_server_drain.restype = ctypes.c_int
+            L.spike_server_drain.argtypes = [_c_p]
+            L.spike_server_stats.restype = ctypes.c_int
+            L.spike_server_stats.argtypes = [_c_p, ctypes.POINTER(ServerReport)]
+            L.spike_server_destroy.restype = ctypes.c_int
+            L.spike_server_destroy.argtypes = [_c_p]
+            L.spike_autotune_workspace_size.restype = ctypes.c_int
+            L.spike_autotune_workspace_size.argtypes = [_c_i64, _c_i32, _c_i32, ctypes.POINTER(Opts),
+                                                        ctypes.POINTER(_c_size)]
+            L.spike_autotune.restype = ctypes.c_int
+            L.spike_autotune.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_i32, ctypes.POINTER(Opts),
+                                         _c_p, _c_size, _c_p, _c_i64, _c_p, ctypes.POINTER(TuneResult)]
             L.spike_profile_enable.restype = ctypes.c_int
             L.spike_profile_enable.argtypes = [ctypes.c_int]
             L.spike_profile_report.restype = ctypes.c_int
@@ -318,6 +368,120 @@ class SolveGraph:
         if getattr(self, "g", None) is not None and self.g.value:
             lib().spike_graph_destroy(self.g)
             self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ab, kl, ku, nrhs=1, stream=None, **base):
+    """Pick p and the partition sizing for this matrix and nrhs by timing
+    candidate plans (spike_autotune).  Returns (opts dict, result dict)."""
+    import torch
+    n, ldab = int(ab.shape[0]), int(ab.shape[1])
+    o = make_opts(**base)
+    need = _c_size()
+    rc = lib().spike_autotune_workspace_size(n, int(kl), int(ku), ctypes.byref(o), ctypes.byref(need))
+    if rc != 0:
+        raise SpikeError("spike_autotune_workspace_size", rc)
+    ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device=ab.device)
+    B = torch.zeros((int(nrhs), n), dtype=torch.float64, device=ab.device)
+    res = TuneResult()
+    rc = lib().spike_autotune(n, int(kl), int(ku), ctypes.c_void_p(ab.data_ptr()), ldab, int(nrhs),
+                              ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              ctypes.c_void_p(B.data_ptr()), n, _stream_handle(stream), ctypes.byref(res))
+    if rc != 0:
+        raise SpikeError("spike_autotune", rc)
+    r = res.opts
+    opts = {"p": r.p, "pivot": bool(r.pivot), "precision": "mixed" if r.precision else "fp64",
+            "sizing": "r13" if r.sizing else "equal", "K": r.K, "nrhs_hint": r.nrhs_hint,
+            "nrhs_max": r.nrhs_max}
+    return opts, {"factor_ms": res.factor_ms, "solve_ms": res.solve_ms, "K": res.K,
+                  "candidates": res.candidates}
+
+
+class Server:
+    """Serving runtime (spike_server_*): queued banded solves with resident
+    factorisations, HBM-budgeted admission and continuous batching.  Tensors
+    handed to submit() are kept referenced until release()."""
+
+    def __init__(self, hbm_budget=16 << 30, max_inflight=64, streams=4, batch_window=32):
+        o = ServerOpts()
+        lib().spike_server_default_opts(ctypes.byref(o))
+        o.hbm_budget, o.max_inflight, o.streams, o.batch_window = int(hbm_budget), int(max_inflight), \
+            int(streams), int(batch_window)
+        s = _c_p()
+        rc = lib().spike_server_create(ctypes.byref(o), ctypes.byref(s))
+        if rc != 0:
+            raise SpikeError("spike_server_create", rc)
+        self.s = s
+        self._keep = {}
+
+    def submit(self, matrix_id, ab, kl, ku, B, trans=False, **opts):
+        """Queue op(A) X = B for matrix ``matrix_id`` (band tensor ``ab``,
+        (n, ldab)); B: (nrhs, n) float64 CUDA tensor, solved in place."""
+        if B.dim() == 1:
+            B = B.view(1, -1)
+        n = int(ab.shape[0])
+        if B.shape[1] != n or B.stride(1) != 1:
+            raise ValueError("B must have shape (nrhs, n) with unit column stride")
+        r = Request()
+        r.matrix_id, r.n, r.kl, r.ku = int(matrix_id), n, int(kl), int(ku)
+        r.dAB, r.ldab = ab.data_ptr(), int(ab.shape[1])
+        r.opts = make_opts(**opts)
+        r.nrhs, r.dB = int(B.shape[0]), B.data_ptr()
+        r.ldb = B.stride(0) if B.shape[0] > 1 else n
+        r.trans = 1 if trans else 0
+        t = _c_i64()
+        rc = lib().spike_server_submit(self.s, ctypes.byref(r), ctypes.byref(t))
+        if rc != 0:
+            raise SpikeError("spike_server_submit", rc)
+        self._keep[t.value] = (ab, B)
+        return t.value
+
+    @staticmethod
+    def _st(st):
+        return {"state": st.state, "error": st.error, "info": st.info, "latency_s": st.latency_s}
+
+    def poll(self, ticket):
+        st = RequestStatus()
+        rc = lib().spike_server_poll(self.s, int(ticket), ctypes.byref(st))
+        if rc != 0:
+            raise SpikeError("spike_server_poll", rc)
+        return self._st(st)
+
+    def wait(self, ticket):
+        st = RequestStatus()
+        rc = lib().spike_server_wait(self.s, int(ticket), ctypes.byref(st))
+        if rc != 0:
+            raise SpikeError("spike_server_wait", rc)
+        return self._st(st)
+
+    def release(self, ticket):
+        rc = lib().spike_server_release(self.s, int(ticket))
+        if rc != 0:
+            raise SpikeError("spike_server_release", rc)
+        self._keep.pop(int(ticket), None)
+
+    def drain(self):
+        rc = lib().spike_server_drain(self.s)
+        if rc != 0:
+            raise SpikeError("spike_server_drain", rc)
+
+    def stats(self):
+        r = ServerReport()
+        rc = lib().spike_server_stats(self.s, ctypes.byref(r))
+        if rc != 0:
+            raise SpikeError("spike_server_stats", rc)
+        return {f: getattr(r, f) for f, _ in ServerReport._fields_}
+
+    def close(self):
+        if getattr(self, "s", None) is not None and self.s.value:
+            lib().spike_server_destroy(self.s)
+            self.s = None
+            self._keep.clear()
 
     def __del__(self):
         try:

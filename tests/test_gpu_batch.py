@@ -137,3 +137,21 @@ def test_graph_of_a_batch_replays_match_eager():
     g.close()
     for s in sysl:
         s[4].close()
+
+
+def test_autotune_returns_a_working_plan():
+    import torch
+    from paper_1811_03559_amd import spike
+    n, k = 60000, 16
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(5600), diag_mult=1.05, diag_add=0.0)
+    dab = torch.from_numpy(ab).cuda()
+    opts, res = spike.autotune(dab, k, k, nrhs=2)
+    assert res["candidates"] >= 2 and res["K"] > 0, res
+    assert res["factor_ms"] > 0 and res["solve_ms"] > 0, res
+    F = inputs.rhs(n, 2, inputs.rng_for(5601))
+    fac = spike.Factorization(dab, k, k, **opts)
+    B = torch.from_numpy(F.copy()).cuda()
+    fac.solve_(B)
+    torch.cuda.synchronize()
+    check(ab, k, k, F, B.cpu().numpy(), pivot=False)
+    fac.close()

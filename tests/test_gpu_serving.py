@@ -1,0 +1,82 @@
+"""Serving runtime: queued requests of mixed size, bandwidth, nrhs and
+operation with resident factorisations and HBM-budgeted admission.  Every
+result must equal, bitwise, the same request factored and solved alone."""
+import numpy as np
+import pytest
+
+from gpu_util import check
+from paper_1811_03559_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+POOL = [(2000, 4, 2), (3000, 8, 3), (5000, 16, 5), (2600, 8, 1), (4000, 32, 4), (3300, 16, 7)]
+
+
+def _pool():
+    import torch
+    mats = []
+    for i, (n, k, p) in enumerate(POOL):
+        ab = inputs.band_dominant(n, k, k, inputs.rng_for(6100 + i), diag_mult=1.05, diag_add=0.0)
+        mats.append((ab, torch.from_numpy(ab).cuda(), k, p))
+    return mats
+
+
+def _requests(nreq, seed):
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(len(POOL))), int(rng.integers(1, 5)), bool(rng.random() < 0.3))
+            for _ in range(nreq)]
+
+
+def test_results_same_alone_and_in_the_mix():
+    import torch
+    from paper_1811_03559_amd import spike
+    mats = _pool()
+    reqs = _requests(60, 6200)
+    Fs = [inputs.rhs(POOL[m][0], nr, inputs.rng_for(6300 + i)) for i, (m, nr, _) in enumerate(reqs)]
+    # budget for about three resident factorisations: forces evictions
+    budget = 3 * max(spike.workspace_size(n, k, k, p=p) for n, k, p in POOL)
+    srv = spike.Server(hbm_budget=budget, max_inflight=16, streams=3, batch_window=8)
+    Bs, tickets = [], []
+    for i, (m, nr, tr) in enumerate(reqs):
+        ab, dab, k, p = mats[m]
+        B = torch.from_numpy(Fs[i].copy()).cuda()
+        Bs.append(B)
+        torch.cuda.synchronize()
+        tickets.append(srv.submit(m, dab, k, k, B, trans=tr, p=p))
+    sts = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    for st in sts:
+        assert st["state"] == 2 and st["info"] == 0, st
+    stats = srv.stats()
+    assert stats["completed"] == len(reqs) and stats["evictions"] > 0, stats
+    assert 0 < stats["p50_s"] <= stats["p99_s"] <= stats["max_s"], stats
+    assert stats["hbm_high_water"] <= budget, stats
+    for t in tickets:
+        srv.release(t)
+    srv.close()
+    for i, (m, nr, tr) in enumerate(reqs):
+        ab, dab, k, p = mats[m]
+        fac = spike.Factorization(dab, k, k, p=p)
+        B = torch.from_numpy(Fs[i].copy()).cuda()
+        fac.solve_(B, trans=tr)
+        torch.cuda.synchronize()
+        X = B.cpu().numpy()
+        assert np.array_equal(X, Bs[i].cpu().numpy()), i
+        if i % 10 == 0:
+            check(ab, k, k, Fs[i], X, trans=tr, pivot=False)
+        fac.close()
+
+
+def test_request_larger_than_the_budget_fails_cleanly():
+    import torch
+    from paper_1811_03559_amd import spike
+    n, k = 20000, 16
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(6400))
+    dab = torch.from_numpy(ab).cuda()
+    srv = spike.Server(hbm_budget=1 << 20, max_inflight=4, streams=1)
+    B = torch.from_numpy(inputs.rhs(n, 1, inputs.rng_for(6401))).cuda()
+    torch.cuda.synchronize()
+    t = srv.submit(0, dab, k, k, B, p=4)
+    st = srv.wait(t)
+    assert st["state"] == 3 and st["error"] == -100, st
+    srv.close()

@@ -75,3 +75,63 @@ def test_workspace_grows_with_problem():
     d = spike.workspace_size(20_000, 8, 8, p=4, pivot=True)
     assert a < b < c < d
     assert spike.workspace_size(0, 3, 3) > 0
+
+
+# ctypes mirrors of the header's structs, checked field by field against what
+# a C compiler lays out (gcc on the header itself).
+_STRUCTS = [("spike_opts", "Opts"), ("spike_status", "Status"), ("spike_plan_info", "PlanInfo"),
+            ("spike_kernel_time", "KernelTime"), ("spike_tune_result", "TuneResult"),
+            ("spike_server_opts", "ServerOpts"), ("spike_request", "Request"),
+            ("spike_request_status", "RequestStatus"), ("spike_server_report", "ServerReport")]
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "spike.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS:
+        cls = getattr(spike, pyname)
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for cname, pyname in _STRUCTS:
+        cls = getattr(spike, pyname)
+        assert int(out["%s size" % cname]) == __import__("ctypes").sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(out["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_server_argument_errors_need_no_device():
+    import ctypes
+    L = spike.lib()
+    o = spike.ServerOpts()
+    L.spike_server_default_opts(ctypes.byref(o))
+    assert o.hbm_budget == 16 << 30 and o.max_inflight == 64 and o.streams == 4 and o.batch_window == 32
+    bad = spike.ServerOpts(hbm_budget=1 << 20, max_inflight=0, streams=1, batch_window=1)
+    s = ctypes.c_void_p()
+    assert L.spike_server_create(ctypes.byref(bad), ctypes.byref(s)) == -1
+    bad = spike.ServerOpts(hbm_budget=1 << 20, max_inflight=4, streams=17, batch_window=1)
+    assert L.spike_server_create(ctypes.byref(bad), ctypes.byref(s)) == -1
+    assert L.spike_server_create(None, None) == -2
+    st = spike.RequestStatus()
+    rep = spike.ServerReport()
+    t = ctypes.c_int64()
+    assert L.spike_server_submit(None, None, ctypes.byref(t)) == -1
+    assert L.spike_server_poll(None, 1, ctypes.byref(st)) == -1
+    assert L.spike_server_wait(None, 1, ctypes.byref(st)) == -1
+    assert L.spike_server_release(None, 1) == -1
+    assert L.spike_server_drain(None) == -1
+    assert L.spike_server_stats(None, ctypes.byref(rep)) == -1
+    assert L.spike_server_destroy(None) == -1
