@@ -80,24 +80,30 @@ def merge_tree(p):
     return out
 
 
-def step_work(sizes, k, nrhs, fast_tips):
-    """Algorithmic work of the kernels of one step (kl = ku = k).
+def step_work(sizes, k, nrhs):
+    """Algorithmic work of the kernels of one step (kl = ku = k, FP64,
+    non-pivoting, the MFMA tile path of the factor and the solve).
 
     Factor:
-      k_leaf_factor  block LU, 2 m k^2 flops per partition (plus, without the
-                     tile-engine tips, the spike sweeps: W L-sweep 2 m k^2 and
-                     [V W] U-sweep 4 m k^2 per middle partition);
+      k_flu          block LU/UL of every partition: 2 m k^2 flops; reads the
+                     band and writes the factors (2 x 8 (2k+1) m bytes);
+      k_leaf_factor  truncated spike sweeps: the bottom k x k block of
+                     L^{-1}[0; B^] per middle partition (k^3), and for the
+                     first/last partition a truncated L and U sweep (2 k^3);
       k_ftip_w       W spike L-sweep, 2 m k^2 per middle partition;
       k_ftip_u       [V W] U-sweep, 4 m k^2 per middle partition;
-      k_merge_factor per merge: Schur complement S = I - W_t V_b (2k^3), LU of
-                     S (2/3 k^3), alpha/beta (2k^3 sweeps + 2k^3 product) when
-                     the node has a right neighbour, gamma/delta (6k^3) when it
-                     has a left one, merged tips 2k^3 each (not at the root).
-    Solve (bytes, nrhs = 1 is bandwidth bound): each full sweep streams half
-    the band (k+1 of the 2k+1 diagonals, 8 bytes each); per solve the middle
+      merges         per merge J: Schur complement S = I - Wt Vb (2k^3,
+                     k_mgemm), LU of S (2/3 k^3, k_mlu), alpha/beta when J has
+                     a right neighbour and gamma/delta when it has a left one
+                     (triangular solves 2k^3 each in k_mtrsm, products 2k^3
+                     each in k_mgemm), merged tips 2k^3 each (k_mgemm), none at
+                     the root.
+    Solve (bytes; nrhs = 1 is bandwidth bound): a full sweep streams half the
+    band (k+1 of the 2k+1 diagonals, 8 bytes each); per solve the middle
     partitions make 4 full sweeps and first/last 2 (the paper's sweep table),
-    split 2/2 and 1/1 between the two partition kernels of a solve, each of
-    which also reads and writes the right-hand side once (16 bytes a row per
+    split 2/2 and 1/1 between the two partition kernels of a solve
+    (k_fdstage/k_fretrieve, transpose k_fzsweep/k_fdtstage), each of which
+    also reads and writes the right-hand side once (16 bytes per row and
     column)."""
     p = len(sizes)
     n = sum(sizes)
@@ -105,29 +111,29 @@ def step_work(sizes, k, nrhs, fast_tips):
     ends = n - mid
     band_half = 8.0 * (k + 1)
     k3 = float(k) ** 3
-    mflops = 0.0
+    f_lu = f_trsm = f_gemm = 0.0
     for a, b in merge_tree(p):
         nv, nw = b < p - 1, a > 0
-        f = 2 * k3 + (2.0 / 3.0) * k3
-        if nv:
-            f += 4 * k3
-        if nw:
-            f += 6 * k3
+        f_lu += (2.0 / 3.0) * k3
+        f_gemm += 2 * k3
+        f_trsm += 2 * k3 * (nv + nw)
+        f_gemm += 2 * k3 * (nv + nw)
         if not (a == 0 and b == p - 1):
-            f += 2 * k3 * ((nv and nw) * 2 + nv + nw)
-        mflops += f
+            f_gemm += 2 * k3 * ((nv and nw) * 2 + nv + nw)
     sweep = (2 * mid + ends) * band_half + 16.0 * n * nrhs
     w = {
-        "k_leaf_factor": {"flops": 2.0 * n * k * k + (0.0 if fast_tips else 6.0 * mid * k * k)},
-        "k_merge_factor": {"flops": mflops},
-        "k_leaf_dstage": {"bytes": sweep},
-        "k_leaf_retrieve": {"bytes": sweep},
-        "k_leaf_zsweep": {"bytes": sweep},
-        "k_leaf_dtstage": {"bytes": sweep},
+        "k_flu": {"flops": 2.0 * n * k * k, "bytes": 2 * 8.0 * (2 * k + 1) * n, "engine": "mfma"},
+        "k_leaf_factor": {"flops": k3 * max(p - 2, 0) + 4 * k3},
+        "k_ftip_w": {"flops": 2.0 * mid * k * k, "engine": "mfma"},
+        "k_ftip_u": {"flops": 4.0 * mid * k * k, "engine": "mfma"},
+        "k_mgemm": {"flops": f_gemm, "engine": "mfma"},
+        "k_mlu": {"flops": f_lu, "engine": "mfma"},
+        "k_mtrsm": {"flops": f_trsm, "engine": "mfma"},
+        "k_fdstage": {"bytes": sweep},
+        "k_fretrieve": {"bytes": sweep},
+        "k_fzsweep": {"bytes": sweep},
+        "k_fdtstage": {"bytes": sweep},
     }
-    if fast_tips:
-        w["k_ftip_w"] = {"flops": 2.0 * mid * k * k, "engine": "mfma"}
-        w["k_ftip_u"] = {"flops": 4.0 * mid * k * k, "engine": "mfma"}
     return w
 
 
@@ -173,11 +179,12 @@ def measured_traffic(kernel, workload):
     return None if t is None else t["read_bytes"] + t["write_bytes"]
 
 
-def roofline(name, work, timing, steps, workload):
-    """Roofline entry of one kernel: algorithmic work per launch over its
-    average launch time (launches of one step may differ in size, so the
-    per-step work over the per-step time is used; for one launch a step the
-    two agree)."""
+def roofline(name, work, timing, workload):
+    """Roofline entry of one kernel: algorithmic work per step over its time
+    per step (HIP events around every launch; for a kernel launched once a
+    step this is the work per launch over the average launch time).  A kernel
+    with both flops and bytes is placed against the engine its dense
+    contraction runs on."""
     traffic = measured_traffic(name, workload)
     if work is None:
         return {"kernel": name, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
@@ -185,9 +192,13 @@ def roofline(name, work, timing, steps, workload):
     t_step = timing["ms_per_step"] / 1000.0
     if "flops" in work:
         ach = work["flops"] / t_step / 1e12
-        return {"kernel": name, "bound": work.get("engine", "alu"), "achieved": ach,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                "traffic": traffic, "work_per_step": work["flops"]}
+        out = {"kernel": name, "bound": work.get("engine", "alu"), "achieved": ach,
+               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+               "traffic": traffic, "work_per_step": work["flops"]}
+        if "bytes" in work:
+            out["hbm_gbs"] = work["bytes"] / t_step / 1e9
+            out["hbm_frac"] = out["hbm_gbs"] / HBM_PEAK_GBS
+        return out
     ach = work["bytes"] / t_step / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "work_per_step": work["bytes"]}
@@ -209,6 +220,203 @@ def cpu_baseline(k, n_full, n_sample=150_000):
             "sample_seconds": dt}
 
 
+def _ev():
+    import torch
+    return torch.cuda.Event(enable_timing=True)
+
+
+def _timed(fn, reps=1):
+    """Median device time (ms) of fn() over `reps` runs, HIP events on the
+    current stream (the stream the library launches on)."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0, e1 = _ev(), _ev()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def fwd_err(X, Xt):
+    return float(np.abs(X - Xt).max() / np.abs(Xt).max())
+
+
+def bench_p_sweep(dab, ab, k, F, ps=(250, 500)):
+    """Factor and N/T solve times of the headline system at other partition
+    counts (equal sizes) and with R13 sizing at p = 256."""
+    import torch
+    from paper_1811_03559_amd import spike
+    out = {}
+    dF = torch.from_numpy(F).cuda()
+    for p, sizing in [(pp, "equal") for pp in ps] + [(256, "r13")]:
+        opts = dict(p=p, sizing=sizing, nrhs_hint=1)
+        holder = {}
+
+        def fac():
+            holder["f"] = spike.Factorization(dab, k, k, **opts)
+        t_f = _timed(fac)
+        f = holder["f"]
+        B, Bt = dF.clone(), dF.clone()
+        t_n = _timed(lambda: f.solve_(B))
+        t_t = _timed(lambda: f.solve_(Bt, trans=True))
+        out["p%d_%s" % (p, sizing)] = {
+            "factor_ms": t_f, "solve_ms": t_n, "solve_t_ms": t_t,
+            "step_ms": t_f + t_n + t_t,
+            "sizes_first_mid": spike.plan_query(ab.shape[0], k, k, **opts)["sizes"][:2],
+            "relres_n": relres(ab, k, k, B.cpu().numpy()[0], F[0]),
+            "relres_t": relres(ab, k, k, Bt.cpu().numpy()[0], F[0], trans=True)}
+        f.close()
+    return out
+
+
+def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
+    """Pivoting SPIKE next to non-pivoting SPIKE (with boosting) on the
+    ill-conditioned N(0,1) row-scaled band: errors against the manufactured
+    solution, residuals, and FP64 refinement (<= 3 steps, same factors)."""
+    import torch
+    from paper_1811_03559_amd import inputs, spike
+    ab, kl, ku, Xtrue = inputs.cfg2(n=n, k=k, nrhs=nrhs)
+    F = np.stack([band_matvec(ab, kl, ku, Xtrue[j]) for j in range(nrhs)])
+    dab = torch.from_numpy(ab).cuda()
+    dF = torch.from_numpy(F).cuda()
+    out = {"n": n, "k": k, "nrhs": nrhs}
+    for p in ps:
+        row = {}
+        for label, opts in (("pivoting", dict(pivot=True)), ("non_pivoting", dict(pivot=False)),
+                            ("pivoting_refined", dict(pivot=True, max_refine=3))):
+            holder = {}
+
+            def fac():
+                holder["f"] = spike.Factorization(dab, kl, ku, p=p, nrhs_max=nrhs, **opts)
+            t_f = _timed(fac)
+            f = holder["f"]
+            B = dF.clone()
+            t_s = _timed(lambda: f.solve_(B))
+            X = B.cpu().numpy()
+            info = f.info()
+            row[label] = {"factor_ms": t_f, "solve_ms": t_s,
+                          "relres": max(relres(ab, kl, ku, X[j], F[j]) for j in range(0, nrhs, 5)),
+                          "fwd_err": fwd_err(X, Xtrue), "n_boosts": info["n_boosts"],
+                          "refine_iters": info["refine_iters"], "info": info["info"]}
+            f.close()
+        out["p%d" % p] = row
+    return out
+
+
+def bench_mixed(n=1_000_000, k=128, nrhs=32, p=256):
+    """FP32 block factors and tips with FP64 reduced system, residual and
+    refinement, against plain FP64, both to a backward error of 1e-13."""
+    import torch
+    from paper_1811_03559_amd import inputs, spike
+    ab, kl, ku, F = inputs.cfg3(n=n, k=k, nrhs=nrhs)
+    dab = torch.from_numpy(ab).cuda()
+    dF = torch.from_numpy(F).cuda()
+    out = {"n": n, "k": k, "nrhs": nrhs, "p": p}
+    for label, opts in (("fp64", {}), ("mixed", dict(precision="mixed"))):
+        res = []
+        for _ in range(3):
+            holder = {}
+
+            def fac():
+                holder["f"] = spike.Factorization(dab, kl, ku, p=p, nrhs_max=nrhs, **opts)
+            t_f = _timed(fac)
+            f = holder["f"]
+            B = dF.clone()
+            t_s = _timed(lambda: f.solve_(B))
+            res.append((t_f + t_s, t_f, t_s, f, B))
+        res.sort(key=lambda r: r[0])
+        t, t_f, t_s, f, B = res[1]
+        X = B.cpu().numpy()
+        info = f.info()
+        out[label] = {"total_ms": t, "factor_ms": t_f, "solve_ms": t_s,
+                      "relres": max(relres(ab, kl, ku, X[j], F[j]) for j in range(0, nrhs, 8)),
+                      "refine_iters": info["refine_iters"], "berr": info["berr"]}
+        for r in res:
+            r[3].close()
+    out["speedup"] = out["fp64"]["total_ms"] / out["mixed"]["total_ms"]
+    out["factor_speedup"] = out["fp64"]["factor_ms"] / out["mixed"]["factor_ms"]
+    return out
+
+
+def bench_serving(nreq=1024, budget_gib=64, pool_per_bucket=4, seed=None):
+    """Serving stream: a burst (all requests at t = 0) gives the saturated
+    throughput; Poisson arrivals at 0.5x and 0.9x of it give the latency
+    under load.  Latency is submission (= arrival) to observed completion."""
+    import torch
+    from paper_1811_03559_amd import inputs, spike
+    pool, reqs = inputs.cfg4_requests(nreq, seed, pool_per_bucket)
+    t_gen = time.perf_counter()
+    mats = {}
+    for (cls, k), members in pool.items():
+        for j, (n, sd) in enumerate(members):
+            ab = inputs.cfg4_matrix(cls, k, n, sd)
+            mats[(cls, k, j)] = (ab, torch.from_numpy(ab).cuda())
+    t_gen = time.perf_counter() - t_gen
+    torch.cuda.synchronize()
+    # every request with n <= 2^16 and one in 20 of the rest is checked
+    chk_rng = np.random.default_rng(7)
+    check = [pool[(r["cls"], r["k"])][r["member"]][0] <= (1 << 16) or chk_rng.random() < 0.05
+             for r in reqs]
+
+    def run(rate):
+        srv = spike.Server(hbm_budget=budget_gib << 30, max_inflight=64, streams=4, batch_window=32)
+        arr = np.random.default_rng(11)
+        Bs, Fs, tickets = [], {}, []
+        gen = torch.Generator(device="cuda")
+        for i, r in enumerate(reqs):
+            n = pool[(r["cls"], r["k"])][r["member"]][0]
+            gen.manual_seed(r["rhs_seed"])
+            B = torch.randn(r["nrhs"], n, dtype=torch.float64, device="cuda", generator=gen)
+            if check[i]:
+                Fs[i] = B[:2].cpu().numpy()
+            Bs.append(B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_next = t0
+        for i, r in enumerate(reqs):
+            if rate:
+                t_next += arr.exponential(1.0 / rate)
+                dt = t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            ab, dab = mats[(r["cls"], r["k"], r["member"])]
+            tickets.append(srv.submit(r["id"], dab, r["k"], r["k"], Bs[i], trans=r["trans"],
+                                      pivot=r["cls"] == "piv", precision=r["precision"],
+                                      nrhs_max=64))
+        sts = [srv.wait(t) for t in tickets]
+        t1 = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        worst = {"dom_fp64": 0.0, "dom_mixed": 0.0, "piv": 0.0}
+        for i, r in enumerate(reqs):
+            if not check[i] or sts[i]["state"] != 2:
+                continue
+            ab = mats[(r["cls"], r["k"], r["member"])][0]
+            X = Bs[i][:2].cpu().numpy()
+            e = max(relres(ab, r["k"], r["k"], X[j], Fs[i][j], trans=r["trans"])
+                    for j in range(min(2, r["nrhs"])))
+            key = "piv" if r["cls"] == "piv" else "dom_" + r["precision"]
+            worst[key] = max(worst[key], e)
+        print("[bench] serving rate=%s: %d done in %.2f s" % (rate, st["completed"], t1 - t0),
+              file=sys.stderr, flush=True)
+        return {"requests": len(reqs), "failed": st["failed"], "completed": st["completed"],
+                "wall_s": t1 - t0, "solves_per_s": st["solves_per_s"],
+                "p50_ms": st["p50_s"] * 1e3, "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
+                "factorizations": st["factorizations"], "evictions": st["evictions"],
+                "hbm_high_water_gib": st["hbm_high_water"] / 2.0 ** 30,
+                "checked": int(sum(check)), "max_relres": worst}
+
+    burst = run(None)
+    theta = burst["solves_per_s"]
+    out = {"pool_matrices": len(mats), "generation_s": t_gen, "budget_gib": budget_gib,
+           "burst": burst,
+           "poisson_0.5": run(0.5 * theta), "poisson_0.9": run(0.9 * theta)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,7 +426,11 @@ def main():
     ap.add_argument("--k", type=int, default=160)
     ap.add_argument("--p", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-detail", action="store_true")
+    ap.add_argument("--no-detail", action="store_true",
+                    help="skip every detail section (phase times and the other workloads)")
+    ap.add_argument("--sections", default="psweep,pivoting,mixed,serving",
+                    help="detail sections: psweep, pivoting, mixed, serving")
+    ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -233,6 +445,7 @@ def main():
     import torch
     from paper_1811_03559_amd import inputs, spike
 
+    t_start = time.perf_counter()
     dev = torch.device("cuda:0")
     n, k, p = args.n, args.k, args.p
     t_gen = time.perf_counter()
@@ -271,13 +484,18 @@ def main():
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
 
     # roofline of the kernel with the largest share of a step
-    fast_tips = k <= 256 and p >= 3          # non-pivoting FP64: tile-engine spike tips
-    work = step_work(plan["sizes"], k, 1, fast_tips)
+    work = step_work(plan["sizes"], k, 1)
+    workload = "spike_step_n%d_k%d_p%d" % (n, k, p)
     kernels = {name: {"calls": c, "avg_ms": ms / max(c, 1), "ms_per_step": ms / args.steps}
                for name, (c, ms) in prof.items()}
+    for name, kt in kernels.items():
+        if name in work:
+            r = roofline(name, work[name], kt, workload)
+            kt.update({x: r[x] for x in ("bound", "achieved", "unit", "frac", "traffic")})
+            if "hbm_gbs" in r:
+                kt["hbm_gbs"], kt["hbm_frac"] = r["hbm_gbs"], r["hbm_frac"]
     dom = max(kernels, key=lambda nm: kernels[nm]["ms_per_step"])
-    roof = roofline(dom, work.get(dom), kernels[dom], args.steps,
-                    "spike_step_n%d_k%d_p%d" % (n, k, p))
+    roof = roofline(dom, work.get(dom), kernels[dom], workload)
     detail = {"kernels": kernels, "generation_s": t_gen}
     if not args.no_detail:
         # phase times, checked results, solve bandwidth, nrhs = 64
@@ -305,7 +523,7 @@ def main():
         t_sn = ev[2].elapsed_time(ev[3])
         t_st = ev[4].elapsed_time(ev[5])
         t_s64 = ev[6].elapsed_time(ev[7])
-        solve_bytes = 2 * work["k_leaf_dstage"]["bytes"]
+        solve_bytes = 2 * work["k_fdstage"]["bytes"]
         X = B.cpu().numpy()[0]
         Xt = Bt.cpu().numpy()[0]
         X64 = B64.cpu().numpy()
@@ -321,6 +539,27 @@ def main():
             "info": fac.info(),
         })
         fac.close()
+        secs = set(args.sections.split(",")) if args.sections else set()
+        del B64
+        def note(msg):
+            print("[bench] %s (%.1f s)" % (msg, time.perf_counter() - t_start), file=sys.stderr, flush=True)
+        if "psweep" in secs:
+            note("p sweep")
+            detail["p_sweep"] = bench_p_sweep(dab, ab, k, F)
+        del dab, dF, dF64, ws
+        torch.cuda.empty_cache()
+        if "pivoting" in secs:
+            note("pivoting")
+            detail["pivoting"] = bench_pivoting()
+            torch.cuda.empty_cache()
+        if "mixed" in secs:
+            note("mixed precision")
+            detail["mixed_precision"] = bench_mixed()
+            torch.cuda.empty_cache()
+        if "serving" in secs:
+            note("serving")
+            detail["serving"] = bench_serving(args.serve_requests)
+            torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC, "value": 1000.0 / ms_per_step, "unit": "solves/s", "n_gpus": 1,

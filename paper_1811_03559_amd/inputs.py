@@ -140,3 +140,49 @@ def cfg3(n=1_000_000, k=128, nrhs=32, seed=None):
     rng = rng_for(seed if seed is not None else seed_for(3))
     ab = band_dominant(n, k, k, rng, diag_mult_range=(1.01, 1.5))
     return ab, k, k, rhs(n, nrhs, rng)
+
+
+def cfg4_requests(nreq=1024, seed=None, pool_per_bucket=4):
+    """Request table of the serving stream: n = round(2^U[12, 20]) per pooled
+    matrix, k in {2, 8, 32, 128}, nrhs in {1, 4, 16, 64}, 30% transpose, 50%
+    re-solving a uniformly chosen earlier matrix id, 80% dominant (cfg1
+    recipe) / 20% pivoting-class (cfg2 recipe) matrices, FP64 or FP32 with
+    FP64 refinement half and half for the dominant class (the pivoting class
+    is FP64 only).  Matrices come from a pool of `pool_per_bucket` per
+    (class, k) bucket; every new id factors a pool matrix afresh.
+
+    Returns (pool, reqs): pool[(cls, k)] = list of (n, seed); reqs = list of
+    dicts with id, cls, k, member, nrhs, trans, precision, rhs_seed."""
+    rng = rng_for(seed if seed is not None else seed_for(4))
+    ks = (2, 8, 32, 128)
+    pool = {}
+    for cls in ("dom", "piv"):
+        for k in ks:
+            pool[(cls, k)] = [(int(round(2.0 ** rng.uniform(12.0, 20.0))), int(rng.integers(1 << 31)))
+                              for _ in range(pool_per_bucket)]
+    ids = []
+    reqs = []
+    for i in range(nreq):
+        if ids and rng.random() < 0.5:
+            base = ids[int(rng.integers(len(ids)))]
+            r = dict(base)
+        else:
+            cls = "piv" if rng.random() < 0.2 else "dom"
+            k = ks[int(rng.integers(4))]
+            prec = "mixed" if cls == "dom" and rng.random() < 0.5 else "fp64"
+            r = {"id": len(ids), "cls": cls, "k": k, "member": int(rng.integers(pool_per_bucket)),
+                 "precision": prec}
+            ids.append(dict(r))
+        r["nrhs"] = (1, 4, 16, 64)[int(rng.integers(4))]
+        r["trans"] = bool(rng.random() < 0.3)
+        r["rhs_seed"] = int(rng.integers(1 << 31))
+        reqs.append(r)
+    return pool, reqs
+
+
+def cfg4_matrix(cls, k, n, seed):
+    """One pooled matrix of the serving stream (cfg1 or cfg2 recipe)."""
+    rng = rng_for(seed)
+    if cls == "piv":
+        return band_gaussian_rowscaled(n, k, k, rng)
+    return band_dominant(n, k, k, rng, diag_mult=1.05)
