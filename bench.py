@@ -87,7 +87,7 @@ def step_work(sizes, k, nrhs):
     Factor:
       k_flu          block LU/UL of every partition: 2 m k^2 flops; reads the
                      band and writes the factors (2 x 8 (2k+1) m bytes);
-      k_leaf_factor  truncated spike sweeps: the bottom k x k block of
+      k_ftip_v       truncated spike sweeps: the bottom k x k block of
                      L^{-1}[0; B^] per middle partition (k^3), and for the
                      first/last partition a truncated L and U sweep (2 k^3);
       k_ftip_w       W spike L-sweep, 2 m k^2 per middle partition;
@@ -123,7 +123,7 @@ def step_work(sizes, k, nrhs):
     sweep = (2 * mid + ends) * band_half + 16.0 * n * nrhs
     w = {
         "k_flu": {"flops": 2.0 * n * k * k, "bytes": 2 * 8.0 * (2 * k + 1) * n, "engine": "mfma"},
-        "k_leaf_factor": {"flops": k3 * max(p - 2, 0) + 4 * k3},
+        "k_ftip_v": {"flops": k3 * max(p - 2, 0) + 4 * k3, "engine": "mfma"},
         "k_ftip_w": {"flops": 2.0 * mid * k * k, "engine": "mfma"},
         "k_ftip_u": {"flops": 4.0 * mid * k * k, "engine": "mfma"},
         "k_mgemm": {"flops": f_gemm, "engine": "mfma"},

@@ -139,8 +139,10 @@ int launch_factor(const KParams& k0, const LaunchCfg& c, hipStream_t st) {
     if ((e = c.fp32 ? flu<float>(k, c, st) : flu<double>(k, c, st))) return e;
     k.lu_done = 1;
   }
-  e = c.fp32 ? leaf_factor<float>(c.nb, k, c, st) : leaf_factor<double>(c.nb, k, c, st);
-  if (e) return e;
+  if (!c.flu) {   // after the MFMA block LU the tip sweeps run in fast_factor
+    e = c.fp32 ? leaf_factor<float>(c.nb, k, c, st) : leaf_factor<double>(c.nb, k, c, st);
+    if (e) return e;
+  }
   if (c.fast) {
     e = c.fp32 ? fast_factor<float>(k, c, st) : fast_factor<double>(k, c, st);
     if (e) return e;

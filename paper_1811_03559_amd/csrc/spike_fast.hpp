@@ -75,6 +75,66 @@ __global__ __launch_bounds__(NT) void k_diag_inv(KParams k) {
   diag_inverses<T>(A, dv, blockIdx.y * NT + threadIdx.x, gridDim.y * NT);
 }
 
+// Truncated spike sweeps of every partition (after the MFMA block LU), on
+// the tile engine.  L^{-1}[0; B'] is zero above row m - h (h = the coupling
+// block's height), and its rows from there on depend only on the trailing
+// block of L: the sweep runs on the trailing principal block from the
+// 16-aligned row jv <= m - h.  Middle partitions stop there (k_ftip_u takes
+// the V columns from row m - ku on).  The first partition (normal frame) and
+// the last (reversed frame) also keep the side block (the bottom h rows) for
+// the retrieval stage and take their single tip, the bottom klf rows of
+// U^{-1} L^{-1}[0; B'], from the trailing block of U from the 16-aligned row
+// ju <= m - klf.
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_v(KParams k, int ncg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int li = blockIdx.x / ncg, cg = blockIdx.x % ncg;
+  const LeafDesc L = k.leaves[li];
+  if (L.type == LEAF_SINGLE) return;
+  const bool rev = L.type == LEAF_LAST;
+  const BandAcc<T> A = leaf_band<T>(k, L);
+  const int m = L.m, kl = k.kl, ku = k.ku, kw = k.kw;
+  const int klf = A.kl, kuf = rev ? kl : ku, h = kuf;
+  if (64 * cg >= kuf) return;
+  const T* dv = leaf_dinv<T>(k, L);
+  T* fs = reinterpret_cast<T*>(k.fscr) + L.fscr_off;   // m x kw, ld m
+  // 1. L sweep of [0; B'] on rows [jv, m)
+  const int jv = ((m - h) / 16) * 16, r0 = m - h - jv;
+  BandAcc<T> As = A;
+  As.a += (int64_t)jv * A.ldw;
+  As.m = m - jv;
+  TSrc src;
+  if (!rev) {
+    const double* bh = k.bhat + (int64_t)li * ku * ku;   // B^_i, lower part
+    src = tsrc(bh - r0, 1, 1, ku, r0, r0 + ku);
+  } else {
+    const double* ch = k.chat + (int64_t)(k.p - 2) * kl * kl;   // C^_p, rows reversed
+    src = tsrc(ch + (kl - 1 + r0), 1, -1, kl, r0, r0 + kl);
+  }
+  tile_sweep<T, HT, OP_L_FWD>(As, dv + (int64_t)(jv / 16) * dinv_stride(), src,
+                              tdst(fs + jv, nullptr, is_f64<T>(), 1, m, m - jv, m - jv, m - jv), 64 * cg, kuf, lds);
+  if (L.type == LEAF_MIDDLE) return;
+  __syncthreads();
+  // 2. side block: the bottom h rows of L^{-1}[0; B'], columns of this group
+  T* sd = reinterpret_cast<T*>(k.side) + (rev ? (int64_t)k.side_ld * k.kmax : 0);
+  const int c0 = 64 * cg, nc = min(64, kuf - c0);
+  for (int idx = threadIdx.x; idx < h * nc; idx += NT) {
+    const int r = idx % h, c = c0 + idx / h;
+    sd[r + (int64_t)c * k.side_ld] = fs[(m - h + r) + (int64_t)c * m];
+  }
+  // 3. the tip: bottom klf rows of U^{-1} (L^{-1}[0; B']), rows [ju, m)
+  const int ju = ((m - klf) / 16) * 16, mu = m - ju, bot = m - klf - ju;
+  BandAcc<T> Au = A;
+  Au.a += (int64_t)ju * A.ldw;
+  Au.m = mu;
+  const TSrc su = tsrc(fs + ju, is_f64<T>(), 1, m, jv > ju ? jv - ju : 0, mu);
+  Tips tips{k.tips, kw, ku};
+  TDst du = rev ? tdst(nullptr, tips.Wt(k.p - 1) + (ku - 1), 1, -1, kw, 0, bot, mu)
+                : tdst(nullptr, tips.Vb(0), 1, 1, kw, 0, bot, mu);
+  tile_sweep<T, HT, OP_U_BWD>(Au, dv + (int64_t)(ju / 16) * dinv_stride(), su, du, 64 * cg, kuf, lds);
+}
+
 template <typename T, int HT>
 __global__ __launch_bounds__(NT) void k_ftip_w(KParams k, int ncg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -352,6 +412,13 @@ int run_fast_factor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
   if (!c.flu) {   // the MFMA block LU writes the inverses itself
     ProfScope ps("k_diag_inv", st);
     hipLaunchKernelGGL((k_diag_inv<T>), dim3(k.p, c.dinv_chunks), dim3(NT), 0, st, k);
+    SPIKE_CHECK_LAUNCH();
+  }
+  if (c.flu && k.p > 1) {   // truncated tip sweeps (k_leaf_factor's work after the block LU)
+    const int ncg_v = (k.kmax + 63) / 64;
+    allow_lds_f(k_ftip_v<T, HT>, c.fast_lds);
+    ProfScope ps("k_ftip_v", st);
+    hipLaunchKernelGGL((k_ftip_v<T, HT>), dim3(k.p * ncg_v), dim3(NT), c.fast_lds, st, k, ncg_v);
     SPIKE_CHECK_LAUNCH();
   }
   if (!k.fast_tips) return 0;

@@ -15,6 +15,7 @@
 // The solve stage uses the same factors: right-hand sides are permuted, then
 // swept with L and U (or U^T, L^T and the inverse permutation).
 #pragma once
+#include <type_traits>
 #include "spike_gemv.hpp"
 #include "spike_kernels.hpp"
 
@@ -393,6 +394,188 @@ static __global__ __launch_bounds__(NT) void k_mlu(KParams k, int mbeg) {
   diag_inverses<double>(D, k.sdinv + (int64_t)mi * nbs * dinv_stride(), tid, NT);
 }
 
+// Register-resident variant for order n <= 64 RS, NWR wavefronts: S lives in
+// registers for the whole factorisation (wavefront w holds the columns
+// c = w + NWR cs, lane l the rows l + 64 s), so a column step costs one
+// workgroup barrier and no global traffic.  Rows are not interchanged while
+// eliminating: the pivot of step j is the largest |entry| of column j among
+// the rows not yet chosen (ties to the smallest row index), it is marked
+// chosen, and every other unchosen row is eliminated against it.  Row r
+// chosen at step i becomes row i of P S, so the packed L \ U written out is
+// the same as with interchanges.  The wavefront owning column j + 1 updates
+// that column first and publishes its pivot and multipliers (double-buffered
+// in LDS) before updating its other columns.
+constexpr int NWR = 8;
+struct MluDiagAcc {   // 16 x 16 diagonal blocks of P S, kept in LDS
+  const double* d;
+  int m;
+  __device__ __forceinline__ double at(int i, int c) const { return d[(i >> 4) * 272 + (i & 15) * 17 + (c & 15)]; }
+  __device__ __forceinline__ bool in(int, int) const { return true; }
+};
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <int CS, int RS>
+__global__ __launch_bounds__(NWR * 64) void k_mlu_reg(KParams k, int mbeg) {
+  __shared__ double s_l[2][RS * 64];      // multipliers of the current / next step
+  __shared__ int s_p[2];                  // pivot rows
+  __shared__ double s_dg[RS * 4 * 272];   // diagonal 16 x 16 blocks of P S
+  __shared__ int s_zero;
+  const MergeDesc J = k.merges[mbeg + blockIdx.x];
+  const int n = k.ku, mi = J.mif;
+  double* S = k.sfac + (int64_t)mi * n * n;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+  if (tid == 0) s_zero = 0;
+
+  double a[CS][RS];
+  int rstep[RS];        // step at which the row was chosen
+  unsigned done = 0;    // bit s: row lane + 64 s chosen, or outside [0, n)
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    rstep[s] = 0;
+    if (lane + 64 * s >= n) done |= 1u << s;
+  }
+#pragma unroll
+  for (int cs = 0; cs < CS; ++cs) {
+    const int c = w + NWR * cs;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s;
+      a[cs][s] = (c < n && r < n) ? S[r + (int64_t)c * n] : 0.0;
+    }
+  }
+
+  // pivot and multipliers of this wavefront's column slot CS0 into buffer b
+  auto pivot_col = [&](auto CSI, int b) __attribute__((always_inline)) {
+    constexpr int cs = decltype(CSI)::value;
+    double best = -2.0;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      double v = fabs(a[cs][s]);
+      if (v != v) v = -0.5;
+      if (done & (1u << s)) v = -1.0;
+      if (v > best) {
+        best = v;
+        bi = lane + 64 * s;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(bi);
+    const int sp = p >> 6, lp = p & 63;
+    double piv = 0.0;
+#pragma unroll
+    for (int s = 0; s < RS; ++s)
+      if (s == sp) piv = lane_read(a[cs][s], lp);
+    if (piv == 0.0 && lane == 0) s_zero = 1;
+    const double rp = piv != 0.0 ? 1.0 / piv : 0.0;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s;
+      const bool elim = !(done & (1u << s)) && r != p;
+      const double l = elim ? a[cs][s] * rp : 0.0;
+      if (elim) a[cs][s] = l;
+      s_l[b][r] = l;
+    }
+    if (lane == 0) s_p[b] = p;
+  };
+  // rank-1 update of column slot CSI with pivot row (sp, lp) and multipliers l
+  auto update = [&](auto CSI, int sp, int lp, const double(&l)[RS]) __attribute__((always_inline)) {
+    constexpr int cs = decltype(CSI)::value;
+    double u = 0.0;
+#pragma unroll
+    for (int s = 0; s < RS; ++s)
+      if (s == sp) u = lane_read(a[cs][s], lp);
+#pragma unroll
+    for (int s = 0; s < RS; ++s) a[cs][s] = fma(-l[s], u, a[cs][s]);
+  };
+
+  if (w == 0 && n > 0) pivot_col(std::integral_constant<int, 0>{}, 0);   // order 0 (ku = 0): nothing to do
+  __syncthreads();
+  // step j = NWR cs + t eliminates column j (slot cs of wavefront t)
+  static_for<0, CS>([&](auto CSI) __attribute__((always_inline)) {
+    constexpr int cs = decltype(CSI)::value;
+    for (int t = 0; t < NWR; ++t) {
+      const int j = NWR * cs + t;
+      if (j >= n) break;
+      const int b = j & 1;
+      const int p = __builtin_amdgcn_readfirstlane(s_p[b]);
+      const int sp = p >> 6, lp = p & 63;
+      double l[RS];
+#pragma unroll
+      for (int s = 0; s < RS; ++s) l[s] = s_l[b][lane + 64 * s];
+      if (lane == lp) {
+#pragma unroll
+        for (int s = 0; s < RS; ++s)
+          if (s == sp) {
+            done |= 1u << s;
+            rstep[s] = j;
+          }
+      }
+      // the owner of column j + 1 updates it and publishes its pivot first
+      const bool ahead = j + 1 < n && w == (t + 1) % NWR;
+      const bool ahead_here = ahead && t + 1 < NWR;   // column j + 1 in slot cs
+      if (ahead_here) {
+        update(CSI, sp, lp, l);
+        pivot_col(CSI, b ^ 1);
+      }
+      if constexpr (cs + 1 < CS) {
+        if (ahead && !ahead_here) {
+          update(std::integral_constant<int, cs + 1>{}, sp, lp, l);
+          pivot_col(std::integral_constant<int, cs + 1>{}, b ^ 1);
+        }
+      }
+      // the other columns right of j
+      if (w > t && !ahead_here && w + NWR * cs < n) update(CSI, sp, lp, l);
+      static_for<cs + 1, CS>([&](auto C2) __attribute__((always_inline)) {
+        constexpr int c2 = decltype(C2)::value;
+        if (w + NWR * c2 < n && !(ahead && !ahead_here && c2 == cs + 1)) update(C2, sp, lp, l);
+      });
+      __syncthreads();
+    }
+  });
+
+  // write P S = L U packed, the permutation and the diagonal blocks
+  int* perm = k.sperm + (int64_t)mi * n;
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int r = lane + 64 * s;
+    if (r < n) perm[rstep[s]] = r;
+  }
+#pragma unroll
+  for (int cs = 0; cs < CS; ++cs) {
+    const int c = w + NWR * cs;
+    if (c >= n) continue;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s, i = rstep[s];
+      if (r < n) {
+        S[i + (int64_t)c * n] = a[cs][s];
+        if ((i >> 4) == (c >> 4)) s_dg[(i >> 4) * 272 + (i & 15) * 17 + (c & 15)] = a[cs][s];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && s_zero) atomicMin(&k.status->iface, (unsigned long long)(mi + 1));
+  const int nbs = (n + 15) / 16;
+  diag_inverses<double>(MluDiagAcc{s_dg, n}, k.sdinv + (int64_t)mi * nbs * dinv_stride(), tid, NWR * 64);
+}
+
 // ------------------------------------------------------- beta, delta solves
 // LDS doubles of k_mtrsm<HT>.
 template <int HT>
@@ -651,7 +834,12 @@ int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
     }
     {
       ProfScope ps("k_mlu", st);
-      hipLaunchKernelGGL(k_mlu, dim3(cnt), dim3(NT), lu_lds, st, k, beg);
+      if (k.ku <= 128)
+        hipLaunchKernelGGL((k_mlu_reg<16, 2>), dim3(cnt), dim3(NWR * 64), 0, st, k, beg);
+      else if (k.ku <= 192)
+        hipLaunchKernelGGL((k_mlu_reg<24, 3>), dim3(cnt), dim3(NWR * 64), 0, st, k, beg);
+      else
+        hipLaunchKernelGGL(k_mlu, dim3(cnt), dim3(NT), lu_lds, st, k, beg);
       SPIKE_CHECK_LAUNCH();
     }
     {

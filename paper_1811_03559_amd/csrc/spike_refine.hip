@@ -76,43 +76,76 @@ __global__ __launch_bounds__(RT) void k_copy_cols(const double* S, int64_t lds, 
   }
 }
 
+// Right-hand sides handled per pass over the band (accumulators per thread)
+// and band columns staged per LDS round.
+constexpr int RQ = 16;
+constexpr int RJ = 64;
+
 // R = F - A X, plus per-column max |R| and max |X| (colred[2q], colred[2q+1]).
+// A workgroup owns RT consecutive rows; for every group of RQ right-hand
+// sides it walks the band columns touching those rows once (coalesced along
+// each column), with the matching RJ x RQ slice of X staged in LDS.  Each
+// row's sum runs over the columns in ascending order.
 __global__ __launch_bounds__(RT) void k_residual_n(const double* ab, int64_t ldab, int64_t n, int kl, int ku,
                                                     const double* F, const double* X, int64_t ldx, double* R,
                                                     int64_t ld, int nrhs, unsigned long long* colred,
                                                     const int32_t* skip) {
   if (*skip) return;
+  __shared__ double xs[RJ][RQ + 1];
   const int64_t i0 = (int64_t)blockIdx.x * RT;
   const int64_t i = i0 + threadIdx.x;
   const int64_t jlo = i0 - kl > 0 ? i0 - kl : 0;
   const int64_t jhi = i0 + RT + ku < n ? i0 + RT + ku : n;
   const int lane = threadIdx.x % 64;
-  for (int q = 0; q < nrhs; ++q) {
-    const double* x = X + (int64_t)q * ldx;
-    double acc = 0.0;
-    for (int64_t j = jlo; j < jhi; ++j) {
-      int64_t d = i - j;
-      if (i < n && d <= kl && -d <= ku) acc = fma(ab[(ku + d) + j * ldab], x[j], acc);
+  for (int q0 = 0; q0 < nrhs; q0 += RQ) {
+    const int nq = nrhs - q0 < RQ ? nrhs - q0 : RQ;
+    double acc[RQ];
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) acc[t] = 0.0;
+    for (int64_t jb = jlo; jb < jhi; jb += RJ) {
+      const int nj = jhi - jb < RJ ? (int)(jhi - jb) : RJ;
+      __syncthreads();
+      for (int e = threadIdx.x; e < RJ * RQ; e += RT) {
+        const int jj = e % RJ, t = e / RJ;
+        xs[jj][t] = (jj < nj && t < nq) ? X[(jb + jj) + (int64_t)(q0 + t) * ldx] : 0.0;
+      }
+      __syncthreads();
+      for (int jj = 0; jj < nj; ++jj) {
+        const int64_t j = jb + jj;
+        const int64_t d = i - j;
+        if (i < n && d <= kl && -d <= ku) {
+          const double a = ab[(ku + d) + j * ldab];
+#pragma unroll
+          for (int t = 0; t < RQ; ++t) acc[t] = fma(a, xs[jj][t], acc[t]);
+        }
+      }
     }
-    double r = 0.0, xa = 0.0;
-    if (i < n) {
-      r = F[i + (int64_t)q * ld] - acc;
-      R[i + (int64_t)q * ld] = r;
-      xa = fabs(x[i]);
-    }
-    double ra = fabs(r);
-    for (int off = 32; off > 0; off >>= 1) {
-      ra = fmax(ra, __shfl_xor(ra, off));
-      xa = fmax(xa, __shfl_xor(xa, off));
-    }
-    if (lane == 0) {
-      atomic_max_nonneg(&colred[2 * q], ra);
-      atomic_max_nonneg(&colred[2 * q + 1], xa);
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) {
+      if (t >= nq) break;
+      const int q = q0 + t;
+      double r = 0.0, xa = 0.0;
+      if (i < n) {
+        r = F[i + (int64_t)q * ld] - acc[t];
+        R[i + (int64_t)q * ld] = r;
+        xa = fabs(X[i + (int64_t)q * ldx]);
+      }
+      double ra = fabs(r);
+      for (int off = 32; off > 0; off >>= 1) {
+        ra = fmax(ra, __shfl_xor(ra, off));
+        xa = fmax(xa, __shfl_xor(xa, off));
+      }
+      if (lane == 0) {
+        atomic_max_nonneg(&colred[2 * q], ra);
+        atomic_max_nonneg(&colred[2 * q + 1], xa);
+      }
     }
   }
 }
 
-// R = F - A^T X: wavefront per output row i (band column i of A).
+// R = F - A^T X: wavefront per output row i (band column i of A).  The
+// column is read once per group of RQ right-hand sides; lanes keep partial
+// sums that are reduced across the wavefront at the end.
 __global__ __launch_bounds__(RT) void k_residual_t(const double* ab, int64_t ldab, int64_t n, int kl, int ku,
                                                     const double* F, const double* X, int64_t ldx, double* R,
                                                     int64_t ld, int nrhs, unsigned long long* colred,
@@ -121,19 +154,32 @@ __global__ __launch_bounds__(RT) void k_residual_t(const double* ab, int64_t lda
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t i = (int64_t)blockIdx.x * (RT / 64) + wave;
   if (i >= n) return;
-  for (int q = 0; q < nrhs; ++q) {
-    const double* x = X + (int64_t)q * ldx;
-    double acc = 0.0;
-    for (int s = lane; s < kl + ku + 1; s += 64) {
-      int64_t j = i + s - ku;   // A(j, i) at ab[s + i*ldab]
-      if (j >= 0 && j < n) acc = fma(ab[s + i * ldab], x[j], acc);
+  const int w = kl + ku + 1;
+  for (int q0 = 0; q0 < nrhs; q0 += RQ) {
+    const int nq = nrhs - q0 < RQ ? nrhs - q0 : RQ;
+    double acc[RQ];
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) acc[t] = 0.0;
+    for (int s = lane; s < w; s += 64) {
+      const int64_t j = i + s - ku;   // A(j, i) at ab[s + i*ldab]
+      if (j < 0 || j >= n) continue;
+      const double a = ab[s + i * ldab];
+#pragma unroll
+      for (int t = 0; t < RQ; ++t)
+        if (t < nq) acc[t] = fma(a, X[j + (int64_t)(q0 + t) * ldx], acc[t]);
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) {
-      double r = F[i + (int64_t)q * ld] - acc;
-      R[i + (int64_t)q * ld] = r;
-      atomic_max_nonneg(&colred[2 * q], fabs(r));
-      atomic_max_nonneg(&colred[2 * q + 1], fabs(x[i]));
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) {
+      if (t >= nq) break;
+      double v = acc[t];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) {
+        const int q = q0 + t;
+        double r = F[i + (int64_t)q * ld] - v;
+        R[i + (int64_t)q * ld] = r;
+        atomic_max_nonneg(&colred[2 * q], fabs(r));
+        atomic_max_nonneg(&colred[2 * q + 1], fabs(X[i + (int64_t)q * ldx]));
+      }
     }
   }
 }
