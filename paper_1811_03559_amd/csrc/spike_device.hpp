@@ -22,6 +22,28 @@
 
 namespace spike {
 
+// Loads and stores through an explicitly global (address space 1) or LDS
+// (address space 3) pointer.  Device functions that receive pointers as
+// generic ones would otherwise use flat instructions, which count against
+// the LDS wait counter too, so that every LDS wait would also wait for the
+// global loads in flight.
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+template <typename T>
+__device__ __forceinline__ T sld(const T* p) {
+  return *(const __attribute__((address_space(3))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void sst(T* p, T v) {
+  *(__attribute__((address_space(3))) T*)p = v;
+}
+
 constexpr int NT = 256;      // threads per workgroup of the leaf and merge kernels
 constexpr int NWAVE = NT / 64;
 
@@ -44,6 +66,7 @@ struct BandAcc {
   __device__ __forceinline__ T& at(int i, int c) const {
     return a[(int64_t)(kuw + i - c) + (int64_t)c * ldw];
   }
+  __device__ __forceinline__ T gl(int i, int c) const { return gld(&a[(int64_t)(kuw + i - c) + (int64_t)c * ldw]); }
   __device__ __forceinline__ bool in(int i, int c) const {
     int d = i - c;
     return d <= kl && -d <= kuw;
@@ -62,6 +85,7 @@ struct DenseAcc {
   const int* ipiv;
   int64_t lpld = 0;
   __device__ __forceinline__ T& at(int i, int c) const { return a[i + (int64_t)c * ld]; }
+  __device__ __forceinline__ T gl(int i, int c) const { return gld(&a[i + (int64_t)c * ld]); }
   __device__ __forceinline__ bool in(int, int) const { return true; }
   __device__ __forceinline__ T* lpanel(int, int) const { return nullptr; }
 };

@@ -5,7 +5,7 @@
 // The partition is cut into 16 x 16 tiles; with HT = ceil(max(kl, ku) / 16)
 // the active part of the right-looking elimination is a window of
 // (HT + 1) x (HT + 1) tiles that slides one tile down the diagonal per step.
-// A workgroup has NW = HT + 1 wavefronts; wavefront w owns the tile columns
+// A workgroup has NW = HT + 2 wavefronts; wavefront w owns the tile columns
 // C = w (mod NW) and keeps the HT + 1 window tiles of its current column in
 // MFMA accumulators, so a tile stays in registers from the moment it is read
 // from the caller's band until it is final.  Step j (column block j is the
@@ -96,13 +96,19 @@ __device__ __forceinline__ void lu_inv16(typename Mf<T>::v4& a, typename Mf<T>::
   }
 }
 
+// Wavefronts of k_flu: one per window column plus one, so that a wavefront
+// that finishes its column has one idle step before the next column it owns
+// enters the window, and the loads of that column are in flight meanwhile.
+template <int HT>
+__host__ __device__ constexpr int flu_nw() { return HT + 2; }
+
 // The elimination of one partition; REV: the partition is the last one,
 // held as the LU of its reversal (row and column order reversed).
 template <typename T, int HT, bool REV>
 __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T* lds) {
   using M = Mf<T>;
   using v4 = typename M::v4;
-  constexpr int NW = HT + 1;
+  constexpr int NW = flu_nw<HT>();
   constexpr int PADW = tile_pad();
   constexpr int TS = 16 * PADW;          // one tile in LDS
   constexpr int BUF = (HT + 2) * TS;     // L^{-1}, U^{-1}, raw panel tiles 1..HT
@@ -123,29 +129,41 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
   // order are the identity, entries outside the band zero; `cs` gathers
   // |a| of the real entries (this lane's rows of its column).  Element
   // (i, c) of the block is A(s+i, s+c), or A(s+m-1-i, s+m-1-c) reversed.
-  auto load_tile = [&](int R, int Cc, double& cs) __attribute__((always_inline)) -> v4 {
+  // Issued in two halves so that a batch of tiles has all its loads in
+  // flight before the first value is used: load_raw reads the band entries
+  // (zero outside the band and the order), make_tile forms the tile.
+  auto load_raw = [&](int R, int Cc, double (&av)[4]) __attribute__((always_inline)) {
     const int ln = opaque(lane);
     const int c = 16 * Cc + (ln & 15), i0 = 16 * R + M::row(ln, 0);
     const int64_t gc = REV ? s + m - 1 - c : s + c;
     const double* colp = k.dAB + (int64_t)k.ku + gc * k.ldab - gc + (REV ? s + m - 1 : s);   // + gi
     const double* p0 = REV ? colp - i0 : colp + i0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + DQ * q;
+      const bool ok = i < m && c < m && i - c <= klf && c - i <= kuf;
+      av[q] = ok ? (REV ? p0[-DQ * q] : p0[DQ * q]) : 0.0;
+    }
+  };
+  auto make_tile = [&](int R, int Cc, const double (&av)[4], double& cs) __attribute__((always_inline)) -> v4 {
+    const int ln = opaque(lane);
+    const int c = 16 * Cc + (ln & 15), i0 = 16 * R + M::row(ln, 0);
     v4 v;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = i0 + DQ * q;
-      T xv;
-      if (i >= m || c >= m) {
-        xv = (i == c) ? T(1) : T(0);
-      } else if (i - c > klf || c - i > kuf) {
-        xv = T(0);
-      } else {
-        const double av = REV ? p0[-DQ * q] : p0[DQ * q];
-        xv = (T)av;
-        cs += fabs(av);
-      }
-      v[q] = xv;
+      v[q] = (i >= m || c >= m) ? ((i == c) ? T(1) : T(0)) : (T)av[q];
+      cs += fabs(av[q]);
     }
     return v;
+  };
+  // all HT + 1 window tiles of column Cc from row R0 down, loads batched
+  auto load_column = [&](int R0, int Cc, v4 (&acc)[HT + 1], double& cs) __attribute__((always_inline)) {
+    double av[HT + 1][4];
+#pragma unroll
+    for (int i = 0; i <= HT; ++i) load_raw(R0 + i, Cc, av[i]);
+#pragma unroll
+    for (int i = 0; i <= HT; ++i) acc[i] = make_tile(R0 + i, Cc, av[i], cs);
   };
   auto store_band = [&](int R, int Cc, const v4& v) __attribute__((always_inline)) {
     const int ln = opaque(lane);
@@ -219,8 +237,12 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
     int C = wave;
     v4 acc[HT + 1];
     double cs = 0.0;
+    if (C < nbk) {
+      load_column(C > HT ? C - HT : 0, C, acc, cs);   // rows of its first window step
+    } else {
 #pragma unroll
-    for (int i = 0; i <= HT; ++i) acc[i] = C < nbk ? load_tile(i, C, cs) : v4{T(0), T(0), T(0), T(0)};
+      for (int i = 0; i <= HT; ++i) acc[i] = v4{T(0), T(0), T(0), T(0)};
+    }
     if (wave == 0) panel(0, lds, acc, cs);
     __syncthreads();
 
@@ -231,12 +253,10 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
         // column j is final; take the column entering the window next step
         C += NW;
         cs = 0.0;
-        if (C < nbk) {
-#pragma unroll
-          for (int i = 0; i <= HT; ++i) acc[i] = load_tile(j + 1 + i, C, cs);
-        }
-      } else if (C < nbk) {
-        const v4 nxt = load_tile(j + 1 + HT, C, cs);
+        if (C < nbk) load_column(C - HT, C, acc, cs);   // window from step C - HT = j + 2 on
+      } else if (c <= HT && C < nbk) {
+        double nav[4];
+        load_raw(j + 1 + HT, C, nav);   // used at the end of the step
         const bool next_panel = (c == 1) && (j + 1 < nbk);
         if (next_panel) __builtin_amdgcn_s_setprio(2);
         const v4 zero = {T(0), T(0), T(0), T(0)};
@@ -248,7 +268,7 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
         for (int i = 1; i <= HT; ++i) acc[i] = mm_lds_reg(P + (1 + i) * TS, nz, acc[i]);
 #pragma unroll
         for (int i = 0; i < HT; ++i) acc[i] = acc[i + 1];
-        acc[HT] = nxt;
+        acc[HT] = make_tile(j + 1 + HT, C, nav, cs);
         if (next_panel) {
           panel(j + 1, lds + ((j + 1) & 1) * BUF, acc, cs);
           __builtin_amdgcn_s_setprio(0);
@@ -296,8 +316,8 @@ constexpr size_t flu_lds_bytes() {
 }
 
 template <typename T, int HT>
-__global__ __launch_bounds__((HT + 1) * 64) void k_flu(KParams k) {
-  constexpr int NW = HT + 1;
+__global__ __launch_bounds__(flu_nw<HT>() * 64) void k_flu(KParams k) {
+  constexpr int NW = flu_nw<HT>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int li = blockIdx.x;
@@ -342,7 +362,7 @@ __global__ __launch_bounds__((HT + 1) * 64) void k_flu(KParams k) {
 
 template <typename T, int HT>
 int run_flu(const KParams& k, const LaunchCfg& c, hipStream_t st) {
-  constexpr int NW = HT + 1;
+  constexpr int NW = flu_nw<HT>();
   const size_t lds = flu_lds_bytes<T, HT>();
   hipFuncSetAttribute((const void*)k_flu<T, HT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   ProfScope ps("k_flu", st);

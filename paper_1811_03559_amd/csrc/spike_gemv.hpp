@@ -68,7 +68,7 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
       const int d = FWD ? i - cc : cc - i;   // distance from the diagonal, > 0
       T v = T(0);
       if (ok && cc < m && d <= reach) {
-        v = TRANS ? A.at(cc, i) : A.at(i, cc);
+        v = TRANS ? A.gl(cc, i) : A.gl(i, cc);
       }
       cf[c] = v;
     }
@@ -80,7 +80,7 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) {
       const int c = 4 * g4 + c4;
-      dvv[c4] = TRANS ? D[c * 16 + r16] : D[r16 * 16 + c];
+      dvv[c4] = gld(TRANS ? D + c * 16 + r16 : D + r16 * 16 + c);
     }
   };
 
@@ -96,12 +96,12 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     const int b = blk_of(s);
     T* wb = lds + (s & 1) * 16;
     const bool cur = act && pos < 16 * s + 16;
-    if (cur) wb[row_of(pos) - 16 * b] = rhs - upd;
+    if (cur) sst(wb + row_of(pos) - 16 * b, rhs - upd);
     __syncthreads();
     // x = D_b^{-1} w_b; lane holds x of row 16 b + r16
     T xp = T(0);
 #pragma unroll
-    for (int c4 = 0; c4 < 4; ++c4) xp += dv[0][c4] * wb[4 * g4 + c4];
+    for (int c4 = 0; c4 < 4; ++c4) xp += dv[0][c4] * sld(wb + 4 * g4 + c4);
     xp += __shfl_xor(xp, 16);
     xp += __shfl_xor(xp, 32);
     if (tid < 16 && 16 * b + tid < m) dst.store(16 * b + tid, 0, (double)xp);

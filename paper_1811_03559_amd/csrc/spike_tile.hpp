@@ -102,7 +102,7 @@ struct TSrc {
     bool ok = ((r >= lo1 && r < hi1) || (r >= lo2 && r < hi2)) && (c >= csplit || r >= clo);
     if (!ok) return 0.0;
     int64_t o = (int64_t)r * rs + (int64_t)c * ld;
-    return f64 ? static_cast<const double*>(p)[o] : (double)static_cast<const float*>(p)[o];
+    return f64 ? gld(static_cast<const double*>(p) + o) : (double)gld(static_cast<const float*>(p) + o);
   }
 };
 
@@ -131,10 +131,10 @@ struct TDst {
     int64_t o = (int64_t)rr * rs + (int64_t)c * ld;
     if (f64) {
       double* q = static_cast<double*>(p) + o;
-      *q = sub ? *q - v : v;
+      gst(q, sub ? gld(q) - v : v);
     } else {
       float* q = static_cast<float*>(p) + o;
-      *q = sub ? (float)((double)*q - v) : (float)v;
+      gst(q, sub ? (float)((double)gld(q) - v) : (float)v);
     }
   }
 };
@@ -154,10 +154,10 @@ template <typename T, int OP, typename Acc>
 __device__ __forceinline__ T tile_m(const Acc& A, int i, int c) {
   const int m = A.m;
   if (i < 0 || c < 0 || i >= m || c >= m) return T(0);
-  if (OP == OP_L_FWD) return (i > c && A.in(i, c)) ? A.at(i, c) : T(0);
-  if (OP == OP_U_BWD) return (i <= c && A.in(i, c)) ? A.at(i, c) : T(0);
-  if (OP == OP_UT_FWD) return (c <= i && A.in(c, i)) ? A.at(c, i) : T(0);
-  return (c > i && A.in(c, i)) ? A.at(c, i) : T(0);   // OP_LT_BWD
+  if (OP == OP_L_FWD) return (i > c && A.in(i, c)) ? A.gl(i, c) : T(0);
+  if (OP == OP_U_BWD) return (i <= c && A.in(i, c)) ? A.gl(i, c) : T(0);
+  if (OP == OP_UT_FWD) return (c <= i && A.in(c, i)) ? A.gl(c, i) : T(0);
+  return (c > i && A.in(c, i)) ? A.gl(c, i) : T(0);   // OP_LT_BWD
 }
 
 template <typename T, int HT, int OP, typename Acc>
@@ -183,7 +183,7 @@ __device__ void tile_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
   const int dsrc = (USE_U ? 256 : 0) + (TRANS ? cc * 16 + rr : rr * 16 + cc);
   auto blk = [&](int step) { return FWD ? step : nb - 1 - step; };
   auto load_panel = [&](int j, T* pf) {
-    pf[0] = dinv[(int64_t)j * dinv_stride() + dsrc];
+    pf[0] = gld(dinv + (int64_t)j * dinv_stride() + dsrc);
 #pragma unroll
     for (int s = 1; s <= HT; ++s) {
       const int bi = FWD ? j + s : j - s;
@@ -192,7 +192,7 @@ __device__ void tile_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
   };
   auto store_panel = [&](T* P, const T* pf) {
 #pragma unroll
-    for (int s = 0; s <= HT; ++s) P[s * 16 * PADW + slot] = pf[s];
+    for (int s = 0; s <= HT; ++s) sst(P + s * 16 * PADW + slot, pf[s]);
   };
   auto load_block = [&](int b) -> v4 {
     v4 v;
@@ -224,7 +224,7 @@ __device__ void tile_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     // 1. x_j = D_j^{-1} w_j
     v4 xv = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) xv = M::mma(P[(lane & 15) * PADW + M::row(lane, i)], acc[0][i], xv);
+    for (int i = 0; i < 4; ++i) xv = M::mma(sld(P + (lane & 15) * PADW + M::row(lane, i)), acc[0][i], xv);
     // 2. write x_j, update the pending blocks
     if (colok) {
 #pragma unroll
@@ -235,7 +235,7 @@ __device__ void tile_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int s = 1; s <= HT; ++s)
-          acc[s] = M::mma(-P[(s * 16 + (lane & 15)) * PADW + M::row(lane, i)], xv[i], acc[s]);
+          acc[s] = M::mma(-sld(P + (s * 16 + (lane & 15)) * PADW + M::row(lane, i)), xv[i], acc[s]);
       }
     }
     // 3. next panel into the other buffer
