@@ -93,11 +93,11 @@ def step_work(sizes, k, nrhs):
       k_ftip_w       W spike L-sweep, 2 m k^2 per middle partition;
       k_ftip_u       [V W] U-sweep, 4 m k^2 per middle partition;
       merges         per merge J: Schur complement S = I - Wt Vb (2k^3,
-                     k_mgemm), LU of S (2/3 k^3, k_mlu), alpha/beta when J has
-                     a right neighbour and gamma/delta when it has a left one
-                     (triangular solves 2k^3 each in k_mtrsm, products 2k^3
-                     each in k_mgemm), merged tips 2k^3 each (k_mgemm), none at
-                     the root.
+                     k_mgemm; with Dm = -Wt Wb another 2k^3 when J has a left
+                     neighbour), LU of S (2/3 k^3, k_mlu), beta/delta
+                     (triangular solves 2k^3 each in k_mtrsm), alpha/gamma
+                     (products 2k^3 each in k_mgemm), merged tips 2k^3 each
+                     (k_mgemm), none at the root.
     Solve (bytes; nrhs = 1 is bandwidth bound): a full sweep streams half the
     band (k+1 of the 2k+1 diagonals, 8 bytes each); per solve the middle
     partitions make 4 full sweeps and first/last 2 (the paper's sweep table),
@@ -115,7 +115,7 @@ def step_work(sizes, k, nrhs):
     for a, b in merge_tree(p):
         nv, nw = b < p - 1, a > 0
         f_lu += (2.0 / 3.0) * k3
-        f_gemm += 2 * k3
+        f_gemm += 2 * k3 * (1 + nw)
         f_trsm += 2 * k3 * (nv + nw)
         f_gemm += 2 * k3 * (nv + nw)
         if not (a == 0 and b == p - 1):

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "spike_types.hpp"
 
@@ -27,6 +28,15 @@ namespace spike {
 // generic ones would otherwise use flat instructions, which count against
 // the LDS wait counter too, so that every LDS wait would also wait for the
 // global loads in flight.
+// f(integral_constant<int, i>) for i = B .. E-1, unrolled at compile time.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T gld(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;

@@ -56,25 +56,27 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     if (i < m) rhs = (T)src.load(i, 0);
   }
 
-  // coefficients M(i, 16 b + c), c = 0..15, of this thread's row at step sp
-  auto fetch_cf = [&](int sp, T* cf) {
+  // coefficients M(i, 16 b + c), c = 0..15, of this thread's row at step sp;
+  // the ring keeps every row strictly past the block (distance d >= 1), so
+  // only the band reach and the order bound the entries
+  auto fetch_cf = [&](int sp, T (&cf)[16]) __attribute__((always_inline)) {
     const int pp = pos >= 16 * sp ? pos : pos + RS;
     const int i = row_of(pp);
     const int b = blk_of(sp);
     const bool ok = act && sp < nb && pp >= 16 * sp + 16 && pp < mp && i < m;
+    // valid c: FWD d = i - 16 b - c <= reach; BWD d = 16 b + c - i <= reach, 16 b + c < m
+    const int clo = FWD ? i - 16 * b - reach : 0;
+    const int chi = FWD ? 15 : min(reach + i - 16 * b, m - 1 - 16 * b);
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int cc = 16 * b + c;
-      const int d = FWD ? i - cc : cc - i;   // distance from the diagonal, > 0
       T v = T(0);
-      if (ok && cc < m && d <= reach) {
-        v = TRANS ? A.gl(cc, i) : A.gl(i, cc);
-      }
+      if (ok && c >= clo && c <= chi) v = TRANS ? A.gl(cc, i) : A.gl(i, cc);
       cf[c] = v;
     }
   };
   // entries (r16, 4 g4 + c4) of the inverse of the diagonal block of step sp
-  auto fetch_dv = [&](int sp, T* dvv) {
+  auto fetch_dv = [&](int sp, T (&dvv)[4]) __attribute__((always_inline)) {
     const int b = blk_of(sp < nb ? sp : nb - 1);
     const T* D = dinv + (int64_t)b * dinv_stride() + (USE_U ? 256 : 0);
 #pragma unroll
@@ -84,15 +86,18 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     }
   };
 
-  T cf[PD + 1][16];
-  T dv[PD + 1][4];
+  // ring of NS = PD + 1 prefetched steps; the step loop is unrolled by NS so
+  // that step s always uses slot s mod NS and refills it for step s + NS
+  constexpr int NS = PD + 1;
+  T cf[NS][16];
+  T dv[NS][4];
 #pragma unroll
-  for (int d = 0; d <= PD; ++d) {
+  for (int d = 0; d < NS; ++d) {
     fetch_cf(d, cf[d]);
     fetch_dv(d, dv[d]);
   }
 
-  for (int s = 0; s < nb; ++s) {
+  auto step = [&](int s, T (&cfs)[16], T (&dvs)[4]) __attribute__((always_inline)) {
     const int b = blk_of(s);
     T* wb = lds + (s & 1) * 16;
     const bool cur = act && pos < 16 * s + 16;
@@ -101,7 +106,7 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     // x = D_b^{-1} w_b; lane holds x of row 16 b + r16
     T xp = T(0);
 #pragma unroll
-    for (int c4 = 0; c4 < 4; ++c4) xp += dv[0][c4] * sld(wb + 4 * g4 + c4);
+    for (int c4 = 0; c4 < 4; ++c4) xp += dvs[c4] * sld(wb + 4 * g4 + c4);
     xp += __shfl_xor(xp, 16);
     xp += __shfl_xor(xp, 32);
     if (tid < 16 && 16 * b + tid < m) dst.store(16 * b + tid, 0, (double)xp);
@@ -109,10 +114,10 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
 #pragma unroll
     for (int c = 0; c < 16; ++c) xs[c] = lane_read(xp, c);
     if (act && !cur) {
-      T acc = upd;
+      T a4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int c = 0; c < 16; ++c) acc += cf[0][c] * xs[c];
-      upd = acc;
+      for (int c = 0; c < 16; ++c) a4[c & 3] += cfs[c] * xs[c];
+      upd += (a4[0] + a4[1]) + (a4[2] + a4[3]);
     }
     if (cur) {
       pos += RS;
@@ -123,16 +128,14 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
         if (i < m) rhs = (T)src.load(i, 0);
       }
     }
-    // rotate the prefetch rings and fetch step s + PD + 1
-#pragma unroll
-    for (int d = 0; d < PD; ++d) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) cf[d][c] = cf[d + 1][c];
-#pragma unroll
-      for (int c4 = 0; c4 < 4; ++c4) dv[d][c4] = dv[d + 1][c4];
-    }
-    fetch_cf(s + PD + 1, cf[PD]);
-    fetch_dv(s + PD + 1, dv[PD]);
+    fetch_cf(s + NS, cfs);
+    fetch_dv(s + NS, dvs);
+  };
+  for (int s0 = 0; s0 < nb; s0 += NS) {
+    static_for<0, NS>([&](auto D) __attribute__((always_inline)) {
+      constexpr int d = decltype(D)::value;
+      if (s0 + d < nb) step(s0 + d, cf[d], dv[d]);
+    });
   }
   __syncthreads();   // the last block's LDS reads before the caller reuses LDS
 }

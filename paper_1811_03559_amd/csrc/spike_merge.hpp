@@ -4,18 +4,17 @@
 // E_J = [[I, V_b(L)], [W_t(R), I]] (recursive-reduced-system subsection),
 // solved through its Schur complement S = I - W_t(R) V_b(L).  A level of the
 // tree is factored in five launches, each spread over all merges of the
-// level and over 32 x 32 output tiles (or 64-column groups):
+// level and over 64 x 64 output tiles (or 64-column groups):
 //   1. S = I - W_t(R) V_b(L)   and   Dm = -W_t(R) W_b(L)
 //   2. P S = L U (partial pivoting, one workgroup per merge), the 16 x 16
 //      diagonal-block inverses of L and U and the row permutation
 //   3. beta = S^{-1} V_t(R),  delta = S^{-1} Dm   (blocked substitution)
-//   4. alpha = -V_b(L) beta,  gamma = W_b(L) - V_b(L) delta
-//   5. the boundary tips of J: V_t = -V_t(L) beta, W_b = -W_b(R) gamma,
-//      V_b = V_b(R) - W_b(R) alpha, W_t = W_t(L) - V_t(L) delta.
+//   4. alpha = -V_b(L) beta,  gamma = W_b(L) - V_b(L) delta, and the top
+//      tips of J: V_t = -V_t(L) beta, W_t = W_t(L) - V_t(L) delta
+//   5. the bottom tips of J: V_b = V_b(R) - W_b(R) alpha, W_b = -W_b(R) gamma.
 // The solve stage uses the same factors: right-hand sides are permuted, then
 // swept with L and U (or U^T, L^T and the inverse permutation).
 #pragma once
-#include <type_traits>
 #include "spike_gemv.hpp"
 #include "spike_kernels.hpp"
 
@@ -41,155 +40,178 @@ __device__ __forceinline__ void batched_copy(int total, LD load, ST store) {
   }
 }
 
-// ---------------------------------------------------------------- GEMM jobs
-struct GJob {
-  int M, N, K, addI, on;
-  double alpha, beta;
-  const double* A;
-  int64_t ars, acs;
-  const double* B;
-  int64_t brs, bcs;
-  const double* Cin;
+// ------------------------------------------------- fused merge products
+// The GEMMs of a merge that share their left operand are one product with
+// kw = kl + ku output columns, split into a low part (columns [0, ku)) and a
+// high part (columns [ku, kw)) with their own destinations:
+//   phase 1:  [S | Dm]            = [I | 0]       - W_t(R) [V_b(L) | W_b(L)]
+//   phase 4:  [alpha | gamma]     = [0 | W_b(L)]  - V_b(L) [beta | delta]
+//   phase 5a: [V_t(J) | W_t(J)]   = [0 | W_t(L)]  - V_t(L) [beta | delta]
+//   phase 5b: [V_b(J) | W_b(J)]   = [V_b(R) | 0]  - W_b(R) [alpha | gamma]
+// (phases 4 and 5a need only beta and delta and share one launch).
+struct FJob {
+  int M, K, on_lo, on_hi, addI;
+  const double* A;   // A(i, kk) = A[i + kk lda]
+  int64_t lda;
+  const double* B;   // B(kk, j) = B[kk + j ldb], j < kw
+  int64_t ldb;
+  const double* cin_lo;
+  const double* cin_hi;
   int64_t ldcin;
-  double* C;
+  double* c_lo;
+  double* c_hi;
   int64_t ldc;
 };
 
-__host__ __device__ constexpr int mgemm_jobs(int ph) { return ph == 1 ? 2 : (ph == 4 ? 2 : 4); }
+__host__ __device__ constexpr int fjobs(int ph) { return ph == 45 ? 2 : 1; }
 
-// job `job` of phase `ph` of merge J; coef holds [alpha beta; gamma delta]
-// as a kw x kw block: alpha rows [0,kl) cols [0,ku), beta rows [kl,kw) cols
-// [0,ku), gamma rows [0,kl) cols [ku,kw), delta rows [kl,kw) cols [ku,kw).
-__device__ inline GJob merge_job(const KParams& k, const MergeDesc& J, int ph, int job) {
+__device__ inline FJob fused_job(const KParams& k, const MergeDesc& J, int ph, int job) {
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif;
   const Tips tp{k.tips, kw, ku};
   const bool nv = J.b < k.p - 1, nw = J.a > 0, root = J.a == 0 && J.b == k.p - 1;
-  double* C = k.coef + (int64_t)mi * kw * kw;
-  double* alpha = C;
-  double* beta = C + kl;
-  double* gamma = C + (int64_t)ku * kw;
-  double* delta = C + kl + (int64_t)ku * kw;
-  double* dm = k.qw + (int64_t)mi * kw * kw;   // -W_t(R) W_b(L), ku x kl, ld ku
+  double* coef = k.coef + (int64_t)mi * kw * kw;
   const int jid = k.p + mi;
-  GJob g;
+  FJob g;
   g.addI = 0;
-  g.on = 0;
-  g.alpha = -1.0;
-  g.beta = 0.0;
-  g.Cin = nullptr;
-  g.ldcin = 0;
-  g.ars = 1;
-  g.acs = kw;
-  g.brs = 1;
-  g.bcs = kw;
-  auto set = [&](int M, int N, int K, const double* A, const double* B, double* Cout, int64_t ldc) {
-    g.M = M;
-    g.N = N;
-    g.K = K;
-    g.A = A;
-    g.B = B;
-    g.C = Cout;
-    g.ldc = ldc;
-  };
+  g.cin_lo = nullptr;
+  g.cin_hi = nullptr;
+  g.ldcin = kw;
+  g.lda = kw;
+  g.ldb = kw;
+  g.ldc = kw;
   if (ph == 1) {
-    if (job == 0) {
-      set(ku, ku, kl, tp.Wt(J.right), tp.Vb(J.left), k.sfac + (int64_t)mi * ku * ku, ku);
-      g.addI = 1;
-      g.on = 1;
-    } else {
-      set(ku, kl, kl, tp.Wt(J.right), tp.Wb(J.left), dm, ku);
-      g.on = nw;
-    }
-  } else if (ph == 4) {
-    if (job == 0) {
-      set(kl, ku, ku, tp.Vb(J.left), beta, alpha, kw);
-      g.on = nv;
-    } else {
-      set(kl, kl, ku, tp.Vb(J.left), delta, gamma, kw);
-      g.Cin = tp.Wb(J.left);
-      g.ldcin = kw;
-      g.beta = 1.0;
-      g.on = nw;
-    }
-  } else {
-    if (job == 0) {
-      set(ku, ku, ku, tp.Vt(J.left), beta, tp.Vt(jid), kw);
-      g.on = nv && nw;
-    } else if (job == 1) {
-      set(kl, kl, kl, tp.Wb(J.right), gamma, tp.Wb(jid), kw);
-      g.on = nv && nw;
-    } else if (job == 2) {
-      set(kl, ku, kl, tp.Wb(J.right), alpha, tp.Vb(jid), kw);
-      g.Cin = tp.Vb(J.right);
-      g.ldcin = kw;
-      g.beta = 1.0;
-      g.on = nv;
-    } else {
-      set(ku, kl, ku, tp.Vt(J.left), delta, tp.Wt(jid), kw);
-      g.Cin = tp.Wt(J.left);
-      g.ldcin = kw;
-      g.beta = 1.0;
-      g.on = nw;
-    }
-    if (root) g.on = 0;
+    g.M = ku;
+    g.K = kl;
+    g.A = tp.Wt(J.right);
+    g.B = tp.Vb(J.left);   // [V_b(L) | W_b(L)]
+    g.c_lo = k.sfac + (int64_t)mi * ku * ku;
+    g.c_hi = k.qw + (int64_t)mi * kw * kw;
+    g.ldc = ku;
+    g.addI = 1;
+    g.on_lo = 1;
+    g.on_hi = nw;
+  } else if (ph == 4 || (ph == 45 && job == 0)) {
+    g.M = kl;
+    g.K = ku;
+    g.A = tp.Vb(J.left);
+    g.B = coef + kl;       // [beta | delta]
+    g.c_lo = coef;         // alpha
+    g.c_hi = coef + (int64_t)ku * kw;   // gamma
+    g.cin_hi = tp.Wb(J.left);
+    g.on_lo = nv;
+    g.on_hi = nw;
+  } else if (ph == 45) {
+    g.M = ku;
+    g.K = ku;
+    g.A = tp.Vt(J.left);
+    g.B = coef + kl;       // [beta | delta]
+    g.c_lo = tp.Vt(jid);
+    g.c_hi = tp.Wt(jid);
+    g.cin_hi = tp.Wt(J.left);
+    g.on_lo = nv && nw && !root;
+    g.on_hi = nw && !root;
+  } else {   // 5b
+    g.M = kl;
+    g.K = kl;
+    g.A = tp.Wb(J.right);
+    g.B = coef;            // [alpha | gamma]
+    g.c_lo = tp.Vb(jid);
+    g.c_hi = tp.Wb(jid);
+    g.cin_lo = tp.Vb(J.right);
+    g.on_lo = nv && !root;
+    g.on_hi = nv && nw && !root;
   }
   return g;
 }
 
-// LDS doubles of k_mgemm for inner dimension up to kmax.
-__host__ __device__ constexpr int mgemm_lds_elems(int kmax) {
-  return 32 * (((kmax + 3) & ~3) + 1) + ((kmax + 3) & ~3) * 33;
-}
-
-// One 32 x 32 output tile of one GEMM job per workgroup:
-//   C = beta Cin + alpha A B (+ I), A and B staged whole into LDS.
+// One 64 x 64 output tile per workgroup; wavefront (wi, wj) owns a 32 x 32
+// quarter as 2 x 2 MFMA tiles; K runs in chunks of 16 through double-
+// buffered LDS, the next chunk loaded into registers during the current one.
+constexpr int FG_T = 64, FG_KC = 16, FG_PAD = FG_T + 1;
 template <int PH>
-__global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj) {
+__global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj, int tn) {
   using M = Mf<double>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
-  constexpr int NJ = mgemm_jobs(PH);
+  __shared__ double As[2][FG_KC * FG_PAD];   // As[kk][i]
+  __shared__ double Bs[2][FG_KC * FG_PAD];   // Bs[kk][j]
+  constexpr int NJ = fjobs(PH);
   const int tile = blockIdx.x % tpj, rest = blockIdx.x / tpj;
   const int job = rest % NJ, mm = rest / NJ;
   const MergeDesc J = k.merges[mbeg + mm];
-  const GJob g = merge_job(k, J, PH, job);
-  if (!g.on) return;
-  const int tm = (g.M + 31) / 32, tn = (g.N + 31) / 32;
-  if (tile >= tm * tn) return;
-  const int i0 = (tile % tm) * 32, j0 = (tile / tm) * 32;
-  const int Kp = (g.K + 3) & ~3, pa = Kp + 1;
-  double* As = lds;              // As[i * pa + kk]
-  double* Bs = lds + 32 * pa;    // Bs[kk * 33 + j]
-  const int tid = threadIdx.x;
-  batched_copy<20>(
-      32 * Kp,
-      [&](int idx) {
-        const int i = idx % 32, kk = idx / 32, gi = i0 + i;
-        return (gi < g.M && kk < g.K) ? g.A[(int64_t)gi * g.ars + (int64_t)kk * g.acs] : 0.0;
-      },
-      [&](int idx, double v) { As[(idx % 32) * pa + idx / 32] = v; });
-  batched_copy<20>(
-      32 * Kp,
-      [&](int idx) {
-        const int kk = idx % Kp, gj = j0 + idx / Kp;
-        return (gj < g.N && kk < g.K) ? g.B[(int64_t)kk * g.brs + (int64_t)gj * g.bcs] : 0.0;
-      },
-      [&](int idx, double v) { Bs[(idx % Kp) * 33 + idx / Kp] = v; });
-  __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6, wi = wave & 1, wj = wave >> 1, cl = lane & 15, kq = lane >> 4;
-  M::v4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k4 = 0; k4 < Kp; k4 += 4)
-    acc = M::mma(As[(wi * 16 + cl) * pa + k4 + kq], Bs[(k4 + kq) * 33 + wj * 16 + cl], acc);
+  const FJob g = fused_job(k, J, PH, job);
+  const int kw = k.kw, ku = k.ku;
+  const int i0 = (tile / tn) * FG_T, j0 = (tile % tn) * FG_T;
+  if (i0 >= g.M) return;
+  const bool any_lo = g.on_lo && j0 < ku, any_hi = g.on_hi && j0 + FG_T > ku;
+  if (!any_lo && !any_hi) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave & 1, wj = wave >> 1, cl = lane & 15, kq = lane >> 4;
+  // staging: thread tid loads A(i0 + (e % 64), kc + e / 64) and
+  // B(kc + e % 16, j0 + e / 16) for e = tid + 256 u, u < 4
+  double ra[4], rb[4];
+  auto load = [&](int kc) __attribute__((always_inline)) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = i0 + wi * 16 + M::row(lane, q), j = j0 + wj * 16 + cl;
-    if (i < g.M && j < g.N) {
-      double v = g.alpha * acc[q];
-      if (g.Cin) v += g.beta * g.Cin[i + (int64_t)j * g.ldcin];
-      if (g.addI && i == j) v += 1.0;
-      g.C[i + (int64_t)j * g.ldc] = v;
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + NT * u;
+      const int ai = i0 + (e % FG_T), ak = kc + e / FG_T;
+      ra[u] = (ai < g.M && ak < g.K) ? g.A[ai + (int64_t)ak * g.lda] : 0.0;
+      const int bk = kc + (e % FG_KC), bj = j0 + e / FG_KC;
+      rb[u] = (bk < g.K && bj < kw) ? g.B[bk + (int64_t)bj * g.ldb] : 0.0;
     }
+  };
+  auto store = [&](int b) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + NT * u;
+      As[b][(e / FG_T) * FG_PAD + (e % FG_T)] = ra[u];
+      Bs[b][(e % FG_KC) * FG_PAD + e / FG_KC] = rb[u];
+    }
+  };
+  M::v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = M::v4{0.0, 0.0, 0.0, 0.0};
+  const int nch = (g.K + FG_KC - 1) / FG_KC;
+  if (nch > 0) {
+    load(0);
+    store(0);
   }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int b = ch & 1;
+    if (ch + 1 < nch) load((ch + 1) * FG_KC);
+#pragma unroll
+    for (int k4 = 0; k4 < FG_KC; k4 += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[b][(k4 + kq) * FG_PAD + wi * 32 + a * 16 + cl];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bv[c] = Bs[b][(k4 + kq) * FG_PAD + wj * 32 + c * 16 + cl];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = M::mma(av[a], bv[c], acc[a][c]);
+    }
+    if (ch + 1 < nch) store(b ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wi * 32 + a * 16 + M::row(lane, q), j = j0 + wj * 32 + c * 16 + cl;
+        if (i >= g.M || j >= kw) continue;
+        const bool lo = j < ku;
+        if (lo ? !g.on_lo : !g.on_hi) continue;
+        const int jj = lo ? j : j - ku;
+        double v = -acc[a][c][q];
+        const double* cin = lo ? g.cin_lo : g.cin_hi;
+        if (cin) v += cin[i + (int64_t)jj * g.ldcin];
+        if (g.addI && lo && i == jj) v += 1.0;
+        (lo ? g.c_lo : g.c_hi)[i + (int64_t)jj * g.ldc] = v;
+      }
 }
 
 // ---------------------------------------------------------------- LU of S
@@ -412,14 +434,6 @@ struct MluDiagAcc {   // 16 x 16 diagonal blocks of P S, kept in LDS
   __device__ __forceinline__ double at(int i, int c) const { return d[(i >> 4) * 272 + (i & 15) * 17 + (c & 15)]; }
   __device__ __forceinline__ bool in(int, int) const { return true; }
 };
-
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
 
 template <int CS, int RS>
 __global__ __launch_bounds__(NWR * 64) void k_mlu_reg(KParams k, int mbeg) {
@@ -814,22 +828,19 @@ inline void allow_lds_m(K kernel, size_t lds) {
 template <int HT>
 int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
   const int kmax = k.kmax;
-  const size_t g_lds = (size_t)mgemm_lds_elems(kmax) * 8;
   const size_t lu_lds = (size_t)mlu_lds_elems(k.ku) * 8;
   const size_t tr_lds = (size_t)mtrsm_lds_elems<HT>() * 8 + 2048;
-  allow_lds_m(k_mgemm<1>, g_lds);
-  allow_lds_m(k_mgemm<4>, g_lds);
-  allow_lds_m(k_mgemm<5>, g_lds);
   allow_lds_m(k_mlu, lu_lds);
   allow_lds_m(k_mtrsm<HT>, tr_lds);
-  const int tpj = ((kmax + 31) / 32) * ((kmax + 31) / 32);
   const int ncg = (kmax + 63) / 64;
+  // fused products: rows up to kmax, kw = kl + ku columns, 64 x 64 tiles
+  const int ftn = (k.kw + FG_T - 1) / FG_T, ftiles = ((kmax + FG_T - 1) / FG_T) * ftn;
   for (int l = 0; l + 1 < (int)c.level_off.size(); ++l) {
     const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
     if (cnt <= 0) continue;
     {
       ProfScope ps("k_mgemm", st);
-      hipLaunchKernelGGL((k_mgemm<1>), dim3(cnt * mgemm_jobs(1) * tpj), dim3(NT), g_lds, st, k, beg, tpj);
+      hipLaunchKernelGGL((k_mgemm<1>), dim3(cnt * fjobs(1) * ftiles), dim3(NT), 0, st, k, beg, ftiles, ftn);
       SPIKE_CHECK_LAUNCH();
     }
     {
@@ -849,12 +860,12 @@ int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
     }
     {
       ProfScope ps("k_mgemm", st);
-      hipLaunchKernelGGL((k_mgemm<4>), dim3(cnt * mgemm_jobs(4) * tpj), dim3(NT), g_lds, st, k, beg, tpj);
+      hipLaunchKernelGGL((k_mgemm<45>), dim3(cnt * fjobs(45) * ftiles), dim3(NT), 0, st, k, beg, ftiles, ftn);
       SPIKE_CHECK_LAUNCH();
     }
     {
       ProfScope ps("k_mgemm", st);
-      hipLaunchKernelGGL((k_mgemm<5>), dim3(cnt * mgemm_jobs(5) * tpj), dim3(NT), g_lds, st, k, beg, tpj);
+      hipLaunchKernelGGL((k_mgemm<6>), dim3(cnt * fjobs(6) * ftiles), dim3(NT), 0, st, k, beg, ftiles, ftn);
       SPIKE_CHECK_LAUNCH();
     }
   }
