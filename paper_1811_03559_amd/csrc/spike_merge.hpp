@@ -469,28 +469,26 @@ __global__ __launch_bounds__(NWR * 64) void k_mlu_reg(KParams k, int mbeg) {
   // pivot and multipliers of this wavefront's column slot CS0 into buffer b
   auto pivot_col = [&](auto CSI, int b) __attribute__((always_inline)) {
     constexpr int cs = decltype(CSI)::value;
+    // candidates: |a| of unchosen rows (NaN as -0.5), chosen rows -1; the
+    // maximum over the wavefront, then the smallest row holding it
+    double v[RS];
     double best = -2.0;
-    int bi = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < RS; ++s) {
-      double v = fabs(a[cs][s]);
-      if (v != v) v = -0.5;
-      if (done & (1u << s)) v = -1.0;
-      if (v > best) {
-        best = v;
-        bi = lane + 64 * s;
-      }
+      double x = fabs(a[cs][s]);
+      if (x != x) x = -0.5;
+      if (done & (1u << s)) x = -1.0;
+      v[s] = x;
+      best = fmax(best, x);
     }
+    const double vmax = wave_max_f64(best);
+    int p = 0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
+    for (int s = RS - 1; s >= 0; --s) {
+      const unsigned long long hit = __ballot(v[s] == vmax);
+      if (hit) p = 64 * s + (int)__builtin_ctzll(hit);
     }
-    const int p = __builtin_amdgcn_readfirstlane(bi);
+    p = __builtin_amdgcn_readfirstlane(p);
     const int sp = p >> 6, lp = p & 63;
     double piv = 0.0;
 #pragma unroll

@@ -74,6 +74,34 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One DPP step of a max-reduction of a double: lane l combines its value with
+// the value the DPP pattern `CTRL` routes to it (its own value where the
+// pattern has no source lane).
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_max_step(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  const int slo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, BANK_MASK, false);
+  const int shi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, BANK_MASK, false);
+  const double o = __longlong_as_double(((long long)shi << 32) | (long long)(unsigned int)slo);
+  return fmax(v, o);
+}
+
+// Maximum of v over the wavefront, returned uniformly (lane 63 gathers the
+// maximum through row shifts within rows of 16 lanes and row broadcasts).
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = dpp_max_step<0x111, 0xf, 0xf>(v);   // row_shr:1
+  v = dpp_max_step<0x112, 0xf, 0xf>(v);   // row_shr:2
+  v = dpp_max_step<0x114, 0xf, 0xf>(v);   // row_shr:4
+  v = dpp_max_step<0x118, 0xf, 0xf>(v);   // row_shr:8
+  v = dpp_max_step<0x142, 0xa, 0xf>(v);   // row_bcast:15
+  v = dpp_max_step<0x143, 0xc, 0xf>(v);   // row_bcast:31
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 // Uniform read of lane `src` (src uniform across the wavefront).
 template <typename T>
 __device__ __forceinline__ T lane_read(T v, int src) {
