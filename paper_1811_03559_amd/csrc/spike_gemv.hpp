@@ -17,6 +17,11 @@
 //      right-hand side is only combined with its accumulated update when the
 //      row becomes current, HT steps later, so no load latency lies on the
 //      chain of block steps.
+// For U^T and L^T a row's 16 coefficients lie along one band column, so a
+// thread reading its own row would touch a different cache line in every
+// lane.  There the coefficients of a step are loaded cooperatively (16
+// consecutive lanes per row, one cache line per 16 lanes), staged through
+// a double-buffered LDS block one step ahead, and read back per row.
 // Operations, as for the tile engine: L X (unit lower, forward), U X (upper,
 // backward), U^T X (forward) and L^T X (unit, backward).
 #pragma once
@@ -26,8 +31,8 @@
 
 namespace spike {
 
-// LDS elements (of T) used by gemv_sweep.
-__host__ __device__ constexpr int gemv_lds_elems() { return 32; }
+// LDS elements (of T) used by gemv_sweep<HT> (at most tile_lds_elems(HT)).
+__host__ __device__ constexpr int gemv_lds_elems(int HT) { return 32 + 2 * 16 * HT * 17; }
 
 template <typename T, int HT, int OP, typename Acc>
 __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const TDst& dst, T* lds) {
@@ -93,11 +98,45 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
   T dv[NS][4];
 #pragma unroll
   for (int d = 0; d < NS; ++d) {
-    fetch_cf(d, cf[d]);
+    if constexpr (!TRANS) fetch_cf(d, cf[d]);
     fetch_dv(d, dv[d]);
   }
 
-  auto step = [&](int s, T (&cfs)[16], T (&dvs)[4]) __attribute__((always_inline)) {
+  // transposed operators: cooperative loads of the coefficients of step sp
+  // (element e = 16 q + c: row q of the ring past the block, column c),
+  // staged in LDS block (sp & 1) one step before they are used
+  constexpr int NQ = 16 * HT;                  // ring rows past the block
+  constexpr int CPT = (NQ * 16 + NT - 1) / NT;   // staged coefficients per thread
+  constexpr int CP = 17;                       // LDS pitch of a row
+  T* cfl = lds + 32;
+  T stg[NS][CPT];
+  auto stage_load = [&](int sp, T (&r)[CPT]) __attribute__((always_inline)) {
+    const int b = blk_of(sp < nb ? sp : nb - 1);
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = tid + NT * u, q = e >> 4, c = e & 15;
+      const int pp = 16 * sp + 16 + q, i = row_of(pp), cc = 16 * b + c;
+      const int d = FWD ? i - cc : cc - i;
+      T v = T(0);
+      if (q < NQ && sp < nb && pp < mp && i < m && cc < m && d >= 1 && d <= reach) v = A.gl(cc, i);
+      r[u] = v;
+    }
+  };
+  auto stage_store = [&](int sp, const T (&r)[CPT]) __attribute__((always_inline)) {
+    T* blk = cfl + (sp & 1) * NQ * CP;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = tid + NT * u, q = e >> 4, c = e & 15;
+      if (q < NQ) sst(blk + q * CP + c, r[u]);
+    }
+  };
+  if constexpr (TRANS) {
+#pragma unroll
+    for (int d = 0; d < NS; ++d) stage_load(d, stg[d]);
+    stage_store(0, stg[0]);   // made visible by the first step's barrier
+  }
+
+  auto step = [&](int s, T (&cfs)[16], T (&dvs)[4], T (&stg_s)[CPT], T (&stg_n)[CPT]) __attribute__((always_inline)) {
     const int b = blk_of(s);
     T* wb = lds + (s & 1) * 16;
     const bool cur = act && pos < 16 * s + 16;
@@ -114,9 +153,18 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
 #pragma unroll
     for (int c = 0; c < 16; ++c) xs[c] = lane_read(xp, c);
     if (act && !cur) {
+      T cv[16];
+      if constexpr (TRANS) {
+        const T* row = cfl + (s & 1) * NQ * CP + (pos - 16 * s - 16) * CP;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) cv[c] = sld(row + c);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) cv[c] = cfs[c];
+      }
       T a4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a4[c & 3] += cfs[c] * xs[c];
+      for (int c = 0; c < 16; ++c) a4[c & 3] += cv[c] * xs[c];
       upd += (a4[0] + a4[1]) + (a4[2] + a4[3]);
     }
     if (cur) {
@@ -128,13 +176,21 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
         if (i < m) rhs = (T)src.load(i, 0);
       }
     }
-    fetch_cf(s + NS, cfs);
+    if constexpr (TRANS) {
+      // step s + 1's coefficients (loaded NS - 1 steps ago) into the other
+      // LDS block, read after the next barrier; then this slot's registers
+      // start the loads of step s + NS
+      stage_store(s + 1, stg_n);
+      stage_load(s + NS, stg_s);
+    } else {
+      fetch_cf(s + NS, cfs);
+    }
     fetch_dv(s + NS, dvs);
   };
   for (int s0 = 0; s0 < nb; s0 += NS) {
     static_for<0, NS>([&](auto D) __attribute__((always_inline)) {
       constexpr int d = decltype(D)::value;
-      if (s0 + d < nb) step(s0 + d, cf[d], dv[d]);
+      if (s0 + d < nb) step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS]);
     });
   }
   __syncthreads();   // the last block's LDS reads before the caller reuses LDS
