@@ -217,12 +217,15 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
 #pragma unroll
       for (int off = 8; off > 0; off >>= 1) t = fmax(t, __shfl_xor(t, off));
       nmax = fmax(nmax, t);
-#pragma unroll
-      for (int i = 1; i <= HT; ++i) lds_put(Pn + (1 + i) * TS, acc[i]);
+      // the diagonal tile's update chain was issued first: its LU runs on
+      // the VALU while the other tiles' MFMAs are still in flight, and the
+      // raw tiles are published after it
       v4 xl, xu;
       lu_inv16<T>(acc[0], xl, xu, boost, 16 * jp, m - 16 * jp, st);
       lds_put(Pn, xl);
       lds_put(Pn + TS, xu);
+#pragma unroll
+      for (int i = 1; i <= HT; ++i) lds_put(Pn + (1 + i) * TS, acc[i]);
       store_band(jp, jp, acc[0]);
       T* D = dv + (int64_t)jp * dinv_stride();
       const int ln = opaque(lane);
