@@ -146,8 +146,8 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     T xp = T(0);
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) xp += dvs[c4] * sld(wb + 4 * g4 + c4);
-    xp += __shfl_xor(xp, 16);
-    xp += __shfl_xor(xp, 32);
+    xp = pair_sum16(xp);
+    xp = pair_sum32(xp);
     if (tid < 16 && 16 * b + tid < m) dst.store(16 * b + tid, 0, (double)xp);
     T xs[16];
 #pragma unroll

@@ -74,6 +74,40 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// v + (the value of lane l ^ 16), resp. l ^ 32, in every lane, with the
+// cross-lane swaps of gfx950 (plain VALU, no LDS crossbar).  Swapping a
+// register with itself leaves the lower lanes' values in the first result
+// and the upper lanes' in the second, so their sum is the pair's sum in the
+// same order in both lanes of the pair.
+__device__ __forceinline__ double pair_sum16(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)(b & 0xffffffffll), hi = (unsigned)((unsigned long long)b >> 32);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double a = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double c = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return a + c;
+}
+__device__ __forceinline__ double pair_sum32(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)(b & 0xffffffffll), hi = (unsigned)((unsigned long long)b >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double a = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double c = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return a + c;
+}
+__device__ __forceinline__ float pair_sum16(float v) {
+  const unsigned x = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_sum32(float v) {
+  const unsigned x = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // One DPP step of a max-reduction of a double: lane l combines its value with
 // the value the DPP pattern `CTRL` routes to it (its own value where the
 // pattern has no source lane).
