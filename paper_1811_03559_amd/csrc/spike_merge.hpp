@@ -651,26 +651,72 @@ __device__ inline void wg_gemm_nr(int M, int N, int K, double alpha, GM A, GM B,
   __syncthreads();
 }
 
+// C = alpha A B + beta C for N <= 16 columns: one 16-column MFMA tile per
+// 16-row block, wavefronts over the row blocks, operands read straight from
+// global memory with 8 k-steps of loads in flight before their MFMAs.
+__device__ inline void wg_gemm16(int M, int N, int K, double alpha, GM A, GM B, double beta, double* C,
+                                 int64_t ldc) {
+  using Mq = Mf<double>;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cl = lane & 15, kq = lane >> 4;
+  const int ntile = (M + 15) / 16;
+  for (int rt = wave; rt < ntile; rt += NT / 64) {
+    const int i = 16 * rt + cl;
+    Mq::v4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = k0 + 4 * u + kq;
+        av[u] = (i < M && kk < K) ? gld(A.p + (int64_t)i * A.rs + (int64_t)kk * A.cs) : 0.0;
+        bv[u] = (cl < N && kk < K) ? gld(B.p + (int64_t)kk * B.rs + (int64_t)cl * B.cs) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = Mq::mma(av[u], bv[u], acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * rt + Mq::row(lane, q);
+      if (r < M && cl < N) {
+        double* c = C + r + (int64_t)cl * ldc;
+        *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Products of the reduced solve: one column with per-thread dot products,
+// up to 16 columns on one MFMA column tile, more in groups of 16.
 __device__ __forceinline__ void mgemm_any(int M, int N, int K, double alpha, GM A, GM B, double beta, double* C,
                                           int64_t ldc, double* lds) {
-  if (N <= 8) wg_gemm_nr(M, N, K, alpha, A, B, beta, C, ldc);
-  else wg_gemm(M, N, K, alpha, A, B, beta, C, ldc, lds);
+  (void)lds;
+  if (N == 1) {
+    wg_gemm_nr(M, N, K, alpha, A, B, beta, C, ldc);
+    return;
+  }
+  for (int c0 = 0; c0 < N; c0 += 16) {
+    GM Bg = B;
+    Bg.p += (int64_t)c0 * B.cs;
+    wg_gemm16(M, min(16, N - c0), K, alpha, A, Bg, beta, C + (int64_t)c0 * ldc, ldc);
+  }
 }
 
 // Bottom-up pass of the reduced solve at merge J (see k_merge_up), with
 // S^{-1} applied as U^{-1} L^{-1} P.
 template <int HT>
-__device__ void mup_body(const KParams& k, int d, int nrhs, double* lds) {
+__device__ void mup_body(const KParams& k, int d, int c0, int nrhs, double* lds) {
   if (solve_idle(k)) return;
   const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
+  const int64_t co = (int64_t)c0 * kw;   // first right-hand side of this column group
   const Tips tp{k.tips, kw, ku};
-  double* nvl = k.nodeval + (int64_t)J.left * kw * R;
-  double* nvr = k.nodeval + (int64_t)J.right * kw * R;
-  double* nvj = k.nodeval + (int64_t)(k.p + mi) * kw * R;
-  double* s = k.st + (int64_t)mi * kw * R;
+  double* nvl = k.nodeval + (int64_t)J.left * kw * R + co;
+  double* nvr = k.nodeval + (int64_t)J.right * kw * R + co;
+  double* nvj = k.nodeval + (int64_t)(k.p + mi) * kw * R + co;
+  double* s = k.st + (int64_t)mi * kw * R + co;
   double* t = s + kl;
-  double* tmp = k.mtmp + (int64_t)mi * kw * R;
+  double* tmp = k.mtmp + (int64_t)mi * kw * R + co;
   const int* perm = k.sperm + (int64_t)mi * ku;
   wg_copy(ku, nrhs, nvr, kw, t, kw);
   wg_copy(kl, nrhs, nvl + ku, kw, s, kw);
@@ -702,30 +748,32 @@ __device__ void mup_body(const KParams& k, int d, int nrhs, double* lds) {
 }
 
 // Top-down pass: interface values of J from its children's (see k_merge_down).
-__device__ inline void mdown_body(const KParams& k, int d, int nrhs, double* lds) {
+__device__ inline void mdown_body(const KParams& k, int d, int c0, int nrhs, double* lds) {
   if (solve_idle(k)) return;
   const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
-  double* x = k.xint + (int64_t)mi * kw * R;
+  const int64_t co = (int64_t)c0 * kw;   // first right-hand side of this column group
+  double* x = k.xint + (int64_t)mi * kw * R + co;
   const double* C = k.coef + (int64_t)mi * kw * kw;
-  wg_copy(kw, nrhs, k.st + (int64_t)mi * kw * R, kw, x, kw);
+  wg_copy(kw, nrhs, k.st + (int64_t)mi * kw * R + co, kw, x, kw);
   __syncthreads();
   if (J.b < k.p - 1)
-    mgemm_any(kw, nrhs, ku, -1.0, gm(C, 1, kw), gm(k.xint + (int64_t)J.b * kw * R + kl, 1, kw), 1.0, x, kw, lds);
+    mgemm_any(kw, nrhs, ku, -1.0, gm(C, 1, kw), gm(k.xint + (int64_t)J.b * kw * R + kl + co, 1, kw), 1.0, x, kw, lds);
   if (J.a > 0)
-    mgemm_any(kw, nrhs, kl, -1.0, gm(C + (int64_t)ku * kw, 1, kw), gm(k.xint + (int64_t)(J.a - 1) * kw * R, 1, kw),
+    mgemm_any(kw, nrhs, kl, -1.0, gm(C + (int64_t)ku * kw, 1, kw), gm(k.xint + (int64_t)(J.a - 1) * kw * R + co, 1, kw),
               1.0, x, kw, lds);
 }
 
 // Transposed reduced solve, first pass (see k_merge_tup).
-__device__ inline void mtup_body(const KParams& k, int d, int nrhs, double* lds) {
+__device__ inline void mtup_body(const KParams& k, int d, int c0, int nrhs, double* lds) {
   if (solve_idle(k)) return;
   const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
-  double* x = k.xint + (int64_t)mi * kw * R;
+  const int64_t co = (int64_t)c0 * kw;   // first right-hand side of this column group
+  double* x = k.xint + (int64_t)mi * kw * R + co;
   for (int ci = k.cptr[mi]; ci < k.cptr[mi + 1]; ++ci) {
     const Contrib c = k.contrib[ci];
-    const double* cr = k.crl + (int64_t)c.merge * kw * R;
+    const double* cr = k.crl + (int64_t)c.merge * kw * R + co;
     if (c.kind == 0) {
       for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
         const int r = idx % ku, q = idx / ku;
@@ -739,9 +787,9 @@ __device__ inline void mtup_body(const KParams& k, int d, int nrhs, double* lds)
     }
     __syncthreads();
   }
-  wg_copy(kw, nrhs, x, kw, k.st + (int64_t)mi * kw * R, kw);
+  wg_copy(kw, nrhs, x, kw, k.st + (int64_t)mi * kw * R + co, kw);
   const double* C = k.coef + (int64_t)mi * kw * kw;
-  double* out = k.crl + (int64_t)d * kw * R;
+  double* out = k.crl + (int64_t)d * kw * R + co;
   if (J.b < k.p - 1) mgemm_any(ku, nrhs, kw, 1.0, gm(C, kw, 1), gm(x, 1, kw), 0.0, out, kw, lds);
   if (J.a > 0) mgemm_any(kl, nrhs, kw, 1.0, gm(C + (int64_t)ku * kw, kw, 1), gm(x, 1, kw), 0.0, out + ku, kw, lds);
 }
@@ -749,17 +797,18 @@ __device__ inline void mtup_body(const KParams& k, int d, int nrhs, double* lds)
 // Transposed reduced solve, second pass (see k_merge_tdown), with S^{-T}
 // applied as P^T L^{-T} U^{-T}.
 template <int HT>
-__device__ void mtdown_body(const KParams& k, int d, int nrhs, double* lds) {
+__device__ void mtdown_body(const KParams& k, int d, int c0, int nrhs, double* lds) {
   if (solve_idle(k)) return;
   const MergeDesc J = k.merges[d];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif, R = k.R;
+  const int64_t co = (int64_t)c0 * kw;   // first right-hand side of this column group
   const Tips tp{k.tips, kw, ku};
-  double* sb = k.st + (int64_t)mi * kw * R;
+  double* sb = k.st + (int64_t)mi * kw * R + co;
   double* tb = sb + kl;
-  double* nvl = k.nodeval + (int64_t)J.left * kw * R;
-  double* nvr = k.nodeval + (int64_t)J.right * kw * R;
-  double* nvj = k.nodeval + (int64_t)(k.p + mi) * kw * R;
-  double* tmp = k.mtmp + (int64_t)mi * kw * R;
+  double* nvl = k.nodeval + (int64_t)J.left * kw * R + co;
+  double* nvr = k.nodeval + (int64_t)J.right * kw * R + co;
+  double* nvj = k.nodeval + (int64_t)(k.p + mi) * kw * R + co;
+  double* tmp = k.mtmp + (int64_t)mi * kw * R + co;
   const int* perm = k.sperm + (int64_t)mi * ku;
   if (J.a > 0) mgemm_any(ku, nrhs, ku, -1.0, gm(tp.Vt(J.left), kw, 1), gm(nvj, 1, kw), 1.0, tb, kw, lds);
   if (J.b < k.p - 1)
@@ -786,23 +835,35 @@ __device__ void mtdown_body(const KParams& k, int d, int nrhs, double* lds) {
 
 // Single-system (merges mbeg + blockIdx.x of one level) and batched launches
 // of the reduced-solve kernels.
+// Every operation of the reduced solve acts on the right-hand sides column by
+// column, so the single-system launches give each merge one workgroup per
+// group of MCG columns (blockIdx.x = merge * groups + group).  A batched
+// launch runs a merge's groups one after the other in one workgroup, with the
+// same arithmetic per column.
+constexpr int MCG = 16;
+__device__ __forceinline__ int mcg_groups(int nrhs) { return (nrhs + MCG - 1) / MCG; }
+
 template <int HT>
 __global__ __launch_bounds__(NT) void k_mup(KParams k, int mbeg, int nrhs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  mup_body<HT>(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+  const int ng = mcg_groups(nrhs), c0 = MCG * (blockIdx.x % ng);
+  mup_body<HT>(k, mbeg + blockIdx.x / ng, c0, min(MCG, nrhs - c0), reinterpret_cast<double*>(smem_raw));
 }
 static __global__ __launch_bounds__(NT) void k_mdown(KParams k, int mbeg, int nrhs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  mdown_body(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+  const int ng = mcg_groups(nrhs), c0 = MCG * (blockIdx.x % ng);
+  mdown_body(k, mbeg + blockIdx.x / ng, c0, min(MCG, nrhs - c0), reinterpret_cast<double*>(smem_raw));
 }
 static __global__ __launch_bounds__(NT) void k_mtup(KParams k, int mbeg, int nrhs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  mtup_body(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+  const int ng = mcg_groups(nrhs), c0 = MCG * (blockIdx.x % ng);
+  mtup_body(k, mbeg + blockIdx.x / ng, c0, min(MCG, nrhs - c0), reinterpret_cast<double*>(smem_raw));
 }
 template <int HT>
 __global__ __launch_bounds__(NT) void k_mtdown(KParams k, int mbeg, int nrhs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  mtdown_body<HT>(k, mbeg + blockIdx.x, nrhs, reinterpret_cast<double*>(smem_raw));
+  const int ng = mcg_groups(nrhs), c0 = MCG * (blockIdx.x % ng);
+  mtdown_body<HT>(k, mbeg + blockIdx.x / ng, c0, min(MCG, nrhs - c0), reinterpret_cast<double*>(smem_raw));
 }
 template <int HT, int KIND>
 __global__ __launch_bounds__(NT) void k_msolve_b(BatchArgs ba) {
@@ -811,10 +872,15 @@ __global__ __launch_bounds__(NT) void k_msolve_b(BatchArgs ba) {
   const int s = batch_sys(ba, blockIdx.x);
   const KParams& k = *ba.kp[s];
   const int d = ba.mbeg[s] + (blockIdx.x - ba.off[s]);
-  if (KIND == 0) mup_body<HT>(k, d, ba.nrhs[s], lds);
-  else if (KIND == 1) mdown_body(k, d, ba.nrhs[s], lds);
-  else if (KIND == 2) mtup_body(k, d, ba.nrhs[s], lds);
-  else mtdown_body<HT>(k, d, ba.nrhs[s], lds);
+  const int nrhs = ba.nrhs[s];
+  for (int c0 = 0; c0 < nrhs; c0 += MCG) {
+    const int nc = min(MCG, nrhs - c0);
+    if (KIND == 0) mup_body<HT>(k, d, c0, nc, lds);
+    else if (KIND == 1) mdown_body(k, d, c0, nc, lds);
+    else if (KIND == 2) mtup_body(k, d, c0, nc, lds);
+    else mtdown_body<HT>(k, d, c0, nc, lds);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- runners
@@ -882,26 +948,26 @@ int run_msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, b
     for (int l = 0; l < L; ++l) {
       const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
       ProfScope ps("k_mup", st);
-      hipLaunchKernelGGL((k_mup<HT>), dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      hipLaunchKernelGGL((k_mup<HT>), dim3(cnt * ((nrhs + MCG - 1) / MCG)), dim3(NT), lds, st, k, beg, nrhs);
       SPIKE_CHECK_LAUNCH();
     }
     for (int l = L - 1; l >= 0; --l) {
       const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
       ProfScope ps("k_mdown", st);
-      hipLaunchKernelGGL(k_mdown, dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      hipLaunchKernelGGL(k_mdown, dim3(cnt * ((nrhs + MCG - 1) / MCG)), dim3(NT), lds, st, k, beg, nrhs);
       SPIKE_CHECK_LAUNCH();
     }
   } else {
     for (int l = 0; l < L; ++l) {
       const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
       ProfScope ps("k_mtup", st);
-      hipLaunchKernelGGL(k_mtup, dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      hipLaunchKernelGGL(k_mtup, dim3(cnt * ((nrhs + MCG - 1) / MCG)), dim3(NT), lds, st, k, beg, nrhs);
       SPIKE_CHECK_LAUNCH();
     }
     for (int l = L - 1; l >= 0; --l) {
       const int beg = c.level_off[l], cnt = c.level_off[l + 1] - beg;
       ProfScope ps("k_mtdown", st);
-      hipLaunchKernelGGL((k_mtdown<HT>), dim3(cnt), dim3(NT), lds, st, k, beg, nrhs);
+      hipLaunchKernelGGL((k_mtdown<HT>), dim3(cnt * ((nrhs + MCG - 1) / MCG)), dim3(NT), lds, st, k, beg, nrhs);
       SPIKE_CHECK_LAUNCH();
     }
   }
