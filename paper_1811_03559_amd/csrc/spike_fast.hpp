@@ -220,19 +220,22 @@ __device__ void fretrieve_body(const KParams& k, int li, double* B, int64_t ldb,
     const double* bh = k.bhat + (int64_t)li * ku * ku;
     const double* xb = k.xint + (int64_t)(li - 1) * kw * R;
     const double* xt = k.xint + (int64_t)li * kw * R + kl;
-    for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
-      int r = idx % kl, q = idx / kl;
-      double acc = 0.0;
-      for (int c = 0; c < kl; ++c) acc += ch[r + (int64_t)c * kl] * xb[c + (int64_t)q * kw];
-      S.at(r, q) = acc;
+    if (nrhs == 1) {
+      for (int idx = threadIdx.x; idx < kl; idx += NT) {
+        double acc = 0.0;
+        for (int c = 0; c < kl; ++c) acc += ch[idx + (int64_t)c * kl] * xb[c];
+        S.at(idx, 0) = acc;
+      }
+      for (int idx = threadIdx.x; idx < ku; idx += NT) {
+        double acc = 0.0;
+        for (int c = 0; c < ku; ++c) acc += bh[idx + (int64_t)c * ku] * xt[c];
+        S.at(m - ku + idx, 0) = acc;
+      }
+      __syncthreads();
+    } else {
+      wg_gemm_cols<double>(kl, nrhs, kl, 1.0, ch, 1, kl, xb, 1, kw, 0.0, &S.at(0, 0), 1, k.sscr_ld);
+      wg_gemm_cols<double>(ku, nrhs, ku, 1.0, bh, 1, ku, xt, 1, kw, 0.0, &S.at(m - ku, 0), 1, k.sscr_ld);
     }
-    for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
-      int r = idx % ku, q = idx / ku;
-      double acc = 0.0;
-      for (int c = 0; c < ku; ++c) acc += bh[r + (int64_t)c * ku] * xt[c + (int64_t)q * kw];
-      S.at(m - ku + r, q) = acc;
-    }
-    __syncthreads();
     // G_i -= L^{-1} [C^ X_{i-1,b}; 0; B^ X_{i+1,t}], then one full U sweep
     leaf_sweep<T, HT, OP_L_FWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, kl, m - ku, m), rhs_dst(X, m, 1), 0, nrhs, lds);
     leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
@@ -243,13 +246,16 @@ __device__ void fretrieve_body(const KParams& k, int li, double* B, int64_t ldb,
   const int h = kuf;
   const T* sd = reinterpret_cast<const T*>(k.side) + (rev ? (int64_t)k.side_ld * k.kmax : 0);
   const double* xn = rev ? k.xint + (int64_t)(k.p - 2) * kw * R : k.xint + kl;
-  for (int idx = threadIdx.x; idx < h * nrhs; idx += NT) {
-    int r = idx % h, q = idx / h;
-    double acc = 0.0;
-    for (int c = 0; c < kuf; ++c) acc += (double)sd[r + (int64_t)c * k.side_ld] * xn[c + (int64_t)q * kw];
-    X.at(m - h + r, q) -= acc;
+  if (nrhs == 1) {
+    for (int r = threadIdx.x; r < h; r += NT) {
+      double acc = 0.0;
+      for (int c = 0; c < kuf; ++c) acc += (double)sd[r + (int64_t)c * k.side_ld] * xn[c];
+      X.at(m - h + r, 0) -= acc;
+    }
+    __syncthreads();
+  } else {
+    wg_gemm_cols<T>(h, nrhs, kuf, -1.0, sd, 1, k.side_ld, xn, 1, kw, 1.0, &X.at(m - h, 0), X.rs, X.ld);
   }
-  __syncthreads();
   (void)klf;
   leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
 }

@@ -20,6 +20,7 @@
 #include <climits>
 
 #include "spike_device.hpp"
+#include "spike_tile.hpp"
 #include "spike_launch.hpp"
 #include "spike_profile.hpp"
 
@@ -454,19 +455,22 @@ __global__ __launch_bounds__(NT) void k_leaf_retrieve(KParams k, double* B, int6
     const double* bh = k.bhat + (int64_t)li * ku * ku;
     const double* xb = k.xint + (int64_t)(li - 1) * kw * R;        // X_{i-1,b}: rows [0, kl)
     const double* xt = k.xint + (int64_t)li * kw * R + kl;         // X_{i+1,t}: rows [kl, kw)
-    for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
-      int r = idx % kl, q = idx / kl;
-      double acc = 0.0;
-      for (int c = 0; c < kl; ++c) acc += ch[r + (int64_t)c * kl] * xb[c + (int64_t)q * kw];
-      S.at(r, q) = acc;
+    if (nrhs == 1) {
+      for (int r = threadIdx.x; r < kl; r += NT) {
+        double acc = 0.0;
+        for (int c = 0; c < kl; ++c) acc += ch[r + (int64_t)c * kl] * xb[c];
+        S.at(r, 0) = acc;
+      }
+      for (int r = threadIdx.x; r < ku; r += NT) {
+        double acc = 0.0;
+        for (int c = 0; c < ku; ++c) acc += bh[r + (int64_t)c * ku] * xt[c];
+        S.at(m - ku + r, 0) = acc;
+      }
+      __syncthreads();
+    } else {
+      wg_gemm_cols<double>(kl, nrhs, kl, 1.0, ch, 1, kl, xb, 1, kw, 0.0, &S.at(0, 0), 1, sld);
+      wg_gemm_cols<double>(ku, nrhs, ku, 1.0, bh, 1, ku, xt, 1, kw, 0.0, &S.at(m - ku, 0), 1, sld);
     }
-    for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
-      int r = idx % ku, q = idx / ku;
-      double acc = 0.0;
-      for (int c = 0; c < ku; ++c) acc += bh[r + (int64_t)c * ku] * xt[c + (int64_t)q * kw];
-      S.at(m - ku + r, q) = acc;
-    }
-    __syncthreads();
     wg_lsweep<NB, T>(A, S, nrhs, 0, lds);
     for (int idx = threadIdx.x; idx < m * nrhs; idx += NT) {
       int r = idx % m, q = idx / m;
@@ -483,13 +487,16 @@ __global__ __launch_bounds__(NT) void k_leaf_retrieve(KParams k, double* B, int6
   const T* sd = reinterpret_cast<const T*>(k.side) + (rev ? (int64_t)k.side_ld * k.kmax : 0);
   const double* xn = rev ? k.xint + (int64_t)(k.p - 2) * kw * R            // X_{p-1,b}
                          : k.xint + kl;                                      // X_{2,t}
-  for (int idx = threadIdx.x; idx < h * nrhs; idx += NT) {
-    int r = idx % h, q = idx / h;
-    double acc = 0.0;
-    for (int c = 0; c < kuf; ++c) acc += (double)sd[r + (int64_t)c * k.side_ld] * xn[c + (int64_t)q * kw];
-    X.at(m - h + r, q) -= acc;
+  if (nrhs == 1) {
+    for (int r = threadIdx.x; r < h; r += NT) {
+      double acc = 0.0;
+      for (int c = 0; c < kuf; ++c) acc += (double)sd[r + (int64_t)c * k.side_ld] * xn[c];
+      X.at(m - h + r, 0) -= acc;
+    }
+    __syncthreads();
+  } else {
+    wg_gemm_cols<T>(h, nrhs, kuf, -1.0, sd, 1, k.side_ld, xn, 1, kw, 1.0, &X.at(m - h, 0), X.rs, X.ld);
   }
-  __syncthreads();
   wg_usweep<NB, T>(A, X, nrhs, 0, lds);
 }
 
@@ -578,18 +585,31 @@ __device__ inline void gform_body(const KParams& k, int mi, const double* B, int
   const double* z = k.ztip + (int64_t)mi * kw * R;
   const double* ch = k.chat + (int64_t)mi * kl * kl;
   const double* bh = k.bhat + (int64_t)mi * ku * ku;
+  if (nrhs == 1) {
+    for (int r = threadIdx.x; r < kl; r += NT) {
+      double acc = B[Lm.start + Lm.m - kl + r];
+      for (int c = 0; c < kl; ++c) acc -= ch[c + (int64_t)r * kl] * z[c];
+      x[r] = acc;
+    }
+    for (int r = threadIdx.x; r < ku; r += NT) {
+      double acc = B[Lr.start + r];
+      for (int c = 0; c < ku; ++c) acc -= bh[c + (int64_t)r * ku] * z[kl + c];
+      x[kl + r] = acc;
+    }
+    return;
+  }
   for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
-    int r = idx % kl, q = idx / kl;
-    double acc = B[(Lm.start + Lm.m - kl + r) + (int64_t)q * ldb];
-    for (int c = 0; c < kl; ++c) acc -= ch[c + (int64_t)r * kl] * z[c + (int64_t)q * kw];
-    x[r + (int64_t)q * kw] = acc;
+    const int r = idx % kl, q = idx / kl;
+    x[r + (int64_t)q * kw] = B[(Lm.start + Lm.m - kl + r) + (int64_t)q * ldb];
   }
   for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
-    int r = idx % ku, q = idx / ku;
-    double acc = B[(Lr.start + r) + (int64_t)q * ldb];
-    for (int c = 0; c < ku; ++c) acc -= bh[c + (int64_t)r * ku] * z[kl + c + (int64_t)q * kw];
-    x[kl + r + (int64_t)q * kw] = acc;
+    const int r = idx % ku, q = idx / ku;
+    x[kl + r + (int64_t)q * kw] = B[(Lr.start + r) + (int64_t)q * ldb];
   }
+  __syncthreads();
+  // x_top -= C^^T z_top, x_bottom -= B^^T z_bottom (transposed coupling blocks)
+  wg_gemm_cols<double>(kl, nrhs, kl, -1.0, ch, kl, 1, z, 1, kw, 1.0, x, 1, kw);
+  wg_gemm_cols<double>(ku, nrhs, ku, -1.0, bh, ku, 1, z + kl, 1, kw, 1.0, x + kl, 1, kw);
 }
 static __global__ __launch_bounds__(NT) void k_gform(KParams k, const double* B, int64_t ldb, int nrhs) {
   gform_body(k, blockIdx.x, B, ldb, nrhs);

@@ -651,41 +651,6 @@ __device__ inline void wg_gemm_nr(int M, int N, int K, double alpha, GM A, GM B,
   __syncthreads();
 }
 
-// C = alpha A B + beta C for N <= 16 columns: one 16-column MFMA tile per
-// 16-row block, wavefronts over the row blocks, operands read straight from
-// global memory with 8 k-steps of loads in flight before their MFMAs.
-__device__ inline void wg_gemm16(int M, int N, int K, double alpha, GM A, GM B, double beta, double* C,
-                                 int64_t ldc) {
-  using Mq = Mf<double>;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cl = lane & 15, kq = lane >> 4;
-  const int ntile = (M + 15) / 16;
-  for (int rt = wave; rt < ntile; rt += NT / 64) {
-    const int i = 16 * rt + cl;
-    Mq::v4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      double av[8], bv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int kk = k0 + 4 * u + kq;
-        av[u] = (i < M && kk < K) ? gld(A.p + (int64_t)i * A.rs + (int64_t)kk * A.cs) : 0.0;
-        bv[u] = (cl < N && kk < K) ? gld(B.p + (int64_t)kk * B.rs + (int64_t)cl * B.cs) : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc = Mq::mma(av[u], bv[u], acc);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = 16 * rt + Mq::row(lane, q);
-      if (r < M && cl < N) {
-        double* c = C + r + (int64_t)cl * ldc;
-        *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[q];
-      }
-    }
-  }
-  __syncthreads();
-}
-
 // Products of the reduced solve: one column with per-thread dot products,
 // up to 16 columns on one MFMA column tile, more in groups of 16.
 __device__ __forceinline__ void mgemm_any(int M, int N, int K, double alpha, GM A, GM B, double beta, double* C,
@@ -696,9 +661,8 @@ __device__ __forceinline__ void mgemm_any(int M, int N, int K, double alpha, GM 
     return;
   }
   for (int c0 = 0; c0 < N; c0 += 16) {
-    GM Bg = B;
-    Bg.p += (int64_t)c0 * B.cs;
-    wg_gemm16(M, min(16, N - c0), K, alpha, A, Bg, beta, C + (int64_t)c0 * ldc, ldc);
+    wg_gemm16x<double>(M, min(16, N - c0), K, alpha, A.p, A.rs, A.cs, B.p + (int64_t)c0 * B.cs, B.rs, B.cs, beta,
+                       C + (int64_t)c0 * ldc, 1, ldc);
   }
 }
 

@@ -136,6 +136,55 @@ __device__ __forceinline__ double wave_max_f64(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
+// C = alpha A B + beta C for N <= 16 columns on one 16-column MFMA tile per
+// 16-row block (wavefronts over the row blocks).  A(i, k) = A[i ars + k acs]
+// (FP64 or FP32, used in FP64), B(k, j) = B[k brs + j bcs],
+// C(i, j) = C[i crs + j ccs]; operands are read straight from global memory
+// with 8 k-steps of loads in flight before their MFMAs.  Ends with a barrier.
+template <typename TA>
+__device__ inline void wg_gemm16x(int M, int N, int K, double alpha, const TA* A, int64_t ars, int64_t acs,
+                                  const double* B, int64_t brs, int64_t bcs, double beta, double* C, int64_t crs,
+                                  int64_t ccs) {
+  using Mq = Mf<double>;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cl = lane & 15, kq = lane >> 4;
+  const int ntile = (M + 15) / 16;
+  for (int rt = wave; rt < ntile; rt += NT / 64) {
+    const int i = 16 * rt + cl;
+    typename Mq::v4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = k0 + 4 * u + kq;
+        av[u] = (i < M && kk < K) ? (double)gld(A + (int64_t)i * ars + (int64_t)kk * acs) : 0.0;
+        bv[u] = (cl < N && kk < K) ? gld(B + (int64_t)kk * brs + (int64_t)cl * bcs) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = Mq::mma(av[u], bv[u], acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * rt + Mq::row(lane, q);
+      if (r < M && cl < N) {
+        double* c = C + (int64_t)r * crs + (int64_t)cl * ccs;
+        *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// The same for any N, in groups of 16 columns.
+template <typename TA>
+__device__ inline void wg_gemm_cols(int M, int N, int K, double alpha, const TA* A, int64_t ars, int64_t acs,
+                                    const double* B, int64_t brs, int64_t bcs, double beta, double* C, int64_t crs,
+                                    int64_t ccs) {
+  for (int c0 = 0; c0 < N; c0 += 16)
+    wg_gemm16x<TA>(M, min(16, N - c0), K, alpha, A, ars, acs, B + (int64_t)c0 * bcs, brs, bcs, beta,
+                   C + (int64_t)c0 * ccs, crs, ccs);
+}
+
 // Uniform read of lane `src` (src uniform across the wavefront).
 template <typename T>
 __device__ __forceinline__ T lane_read(T v, int src) {
