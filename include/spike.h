@@ -302,7 +302,10 @@ typedef struct spike_request {
 
 typedef struct spike_request_status {
     int32_t state;        /* 0 queued, 1 on the device, 2 done, 3 failed     */
-    int32_t error;        /* failure code (-100: larger than the budget)     */
+    int32_t error;        /* failure code: -100 larger than the budget,
+                             -101 the id is resident for a matrix of other
+                             n, kl, ku or dAB; else a spike_factor or
+                             spike_solve_batch code                          */
     int64_t info;         /* spike_status.info of the factorisation          */
     double latency_s;     /* submission to observed completion, -1 if open   */
 } spike_request_status;

@@ -83,6 +83,9 @@ class Pool {
 
 struct Resident {
   int64_t id;
+  int64_t n = 0;               // the matrix it was factored from
+  int32_t kl = 0, ku = 0;
+  const double* dAB = nullptr;
   spike_handle h = nullptr;
   size_t off = 0, bytes = 0;
   int stream = 0;
@@ -170,7 +173,14 @@ struct spike_server_s {
   Resident* resident_for(Req* q, int* err) {
     *err = 0;
     auto it = res.find(q->r.matrix_id);
-    if (it != res.end()) return it->second;
+    if (it != res.end()) {
+      const Resident* r = it->second;
+      if (r->n != q->r.n || r->kl != q->r.kl || r->ku != q->r.ku || r->dAB != q->r.dAB) {
+        *err = -101;   // the id is resident for another matrix
+        return nullptr;
+      }
+      return it->second;
+    }
     size_t need = 0;
     int e = spike_workspace_size(q->r.n, q->r.kl, q->r.ku, &q->r.opts, &need);
     if (e) {
@@ -185,6 +195,10 @@ struct spike_server_s {
     if (!make_room(need, &off)) return nullptr;
     Resident* r = new Resident();
     r->id = q->r.matrix_id;
+    r->n = q->r.n;
+    r->kl = q->r.kl;
+    r->ku = q->r.ku;
+    r->dAB = q->r.dAB;
     r->off = off;
     r->bytes = need;
     r->stream = (int)(std::min_element(load.begin(), load.end()) - load.begin());

@@ -80,3 +80,21 @@ def test_request_larger_than_the_budget_fails_cleanly():
     st = srv.wait(t)
     assert st["state"] == 3 and st["error"] == -100, st
     srv.close()
+
+
+def test_id_reused_for_another_matrix_fails():
+    import torch
+    from paper_1811_03559_amd import spike
+    k = 8
+    ab1 = inputs.band_dominant(3000, k, k, inputs.rng_for(6500))
+    ab2 = inputs.band_dominant(2000, k, k, inputs.rng_for(6501))
+    d1, d2 = torch.from_numpy(ab1).cuda(), torch.from_numpy(ab2).cuda()
+    B1 = torch.from_numpy(inputs.rhs(3000, 1, inputs.rng_for(6502))).cuda()
+    B2 = torch.from_numpy(inputs.rhs(2000, 1, inputs.rng_for(6503))).cuda()
+    torch.cuda.synchronize()
+    srv = spike.Server(hbm_budget=1 << 30, max_inflight=4, streams=1)
+    st1 = srv.wait(srv.submit(7, d1, k, k, B1, p=3))
+    st2 = srv.wait(srv.submit(7, d2, k, k, B2, p=3))
+    assert st1["state"] == 2 and st1["error"] == 0, st1
+    assert st2["state"] == 3 and st2["error"] == -101, st2
+    srv.close()
