@@ -152,11 +152,13 @@ def calib_copy(gib=1.0, reps=3):
 
 
 def kernel_source_digest():
-    """SHA-256 over the library's kernel sources (names and bytes, sorted)."""
+    """SHA-256 over the library's device-code sources: the HIP translation
+    units and headers (names and bytes, sorted); the host-only planner, API,
+    server and profiler units (.cpp) compile to no kernel."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1811_03559_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in sorted(f for f in os.listdir(d) if f.endswith((".hip", ".hpp"))):
         h.update(f.encode())
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
@@ -246,13 +248,15 @@ def fwd_err(X, Xt):
 
 def bench_p_sweep(dab, ab, k, F, ps=(250, 500)):
     """Factor and N/T solve times of the headline system at other partition
-    counts (equal sizes) and with R13 sizing at p = 256."""
+    counts (equal sizes; balanced merge tree and the paper's 2^m + r layout)
+    and with R13 sizing at p = 256."""
     import torch
     from paper_1811_03559_amd import spike
     out = {}
     dF = torch.from_numpy(F).cuda()
-    for p, sizing in [(pp, "equal") for pp in ps] + [(256, "r13")]:
-        opts = dict(p=p, sizing=sizing, nrhs_hint=1)
+    cases = [(pp, "equal", "balanced") for pp in ps] + [(pp, "equal", "paper") for pp in ps]
+    for p, sizing, tree in cases + [(256, "r13", "balanced")]:
+        opts = dict(p=p, sizing=sizing, nrhs_hint=1, tree=tree)
         holder = {}
 
         def fac():
@@ -262,7 +266,8 @@ def bench_p_sweep(dab, ab, k, F, ps=(250, 500)):
         B, Bt = dF.clone(), dF.clone()
         t_n = _timed(lambda: f.solve_(B))
         t_t = _timed(lambda: f.solve_(Bt, trans=True))
-        out["p%d_%s" % (p, sizing)] = {
+        out["p%d_%s%s" % (p, sizing, "_paper_tree" if tree == "paper" else "")] = {
+            "levels": spike.plan_query(ab.shape[0], k, k, **opts)["levels"],
             "factor_ms": t_f, "solve_ms": t_n, "solve_t_ms": t_t,
             "step_ms": t_f + t_n + t_t,
             "sizes_first_mid": spike.plan_query(ab.shape[0], k, k, **opts)["sizes"][:2],

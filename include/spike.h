@@ -83,6 +83,19 @@ typedef struct spike_opts {
                            where SPIKE loses accuracy).  Refinement needs
                            the caller's dAB to stay valid                [-1]    */
     double refine_tol;  /* backward-error target of refinement        [1e-13]    */
+    int32_t tree;       /* shape of the reduced-system merge tree:
+                           0 = balanced: at every level adjacent nodes
+                           pair left to right, an odd last node carries
+                           up; any p.
+                           1 = the paper's flexible-threading layout
+                           (load-balancing section): p = 2^m + r leaves
+                           with 0 <= r <= 2^m - 2; leaves 1..2r (0-based)
+                           are the halves of r inner two-thread
+                           partitions, placed from the second partition
+                           on, and merge first; a complete binary tree
+                           then runs over the 2^m nodes.  Any other p is
+                           an error (-4); with p = 0 the planner's count
+                           is lowered to the nearest admissible one.  [0] */
 } spike_opts;
 
 /* Device-side status, read by spike_info() (blocking copy). */
@@ -112,10 +125,21 @@ SPIKE_API void spike_default_opts(spike_opts *opts);
 /* Host-only planner query.  Writes the plan summary to *out and, when
  * sizes is not NULL, the p partition sizes (int64) in order.  sizes must hold
  * at least p entries when opts->p > 0, else 4096.  Touches no device.
- * Errors: -1 n < 0, -2 kl < 0, -3 ku < 0, -4 bad opts (p < 0, p > n, or a
- * partition smaller than kl+ku, or an unknown mode). */
+ * Errors: -1 n < 0, -2 kl < 0, -3 ku < 0, -4 bad opts (p < 0, p > n, a
+ * partition smaller than kl+ku, an unknown mode, or with tree 1 a p that is
+ * not 2^m + r with r <= 2^m - 2). */
 SPIKE_API int spike_plan_query(int64_t n, int32_t kl, int32_t ku, const spike_opts *opts,
                      spike_plan_info *out, int64_t *sizes);
+
+/* Host-only query of the merge tree the planner builds for these options.
+ * Writes, for each of the p - 1 interface systems in launch order (level 1
+ * first), four int32: the tree level (1 = merges of leaves), the first leaf
+ * a of the merged node, the interface index m (the left child spans leaves
+ * a..m, the right child m+1..b) and the last leaf b.  merges must hold
+ * 4 (p - 1) entries (p as reported by spike_plan_query).  Touches no
+ * device.  Same errors as spike_plan_query. */
+SPIKE_API int spike_plan_tree(int64_t n, int32_t kl, int32_t ku, const spike_opts *opts,
+                    int32_t *merges);
 
 /* Bytes of device workspace spike_factor() needs.  Same errors as
  * spike_plan_query. */

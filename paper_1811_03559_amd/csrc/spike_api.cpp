@@ -361,6 +361,21 @@ int spike_plan_query(int64_t n, int32_t kl, int32_t ku, const spike_opts* opts, 
   return 0;
 }
 
+int spike_plan_tree(int64_t n, int32_t kl, int32_t ku, const spike_opts* opts, int32_t* merges) {
+  spike::Plan pl;
+  int r = plan_for(n, kl, ku, opts, pl);
+  if (r) return r;
+  if (merges)
+    for (size_t d = 0; d < pl.merges.size(); ++d) {
+      const spike::MergeDesc& J = pl.merges[d];
+      merges[4 * d + 0] = J.level;
+      merges[4 * d + 1] = J.a;
+      merges[4 * d + 2] = J.mif;
+      merges[4 * d + 3] = J.b;
+    }
+  return 0;
+}
+
 int spike_workspace_size(int64_t n, int32_t kl, int32_t ku, const spike_opts* opts, size_t* bytes) {
   spike::Plan pl;
   int r = plan_for(n, kl, ku, opts, pl);

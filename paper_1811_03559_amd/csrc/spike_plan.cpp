@@ -6,12 +6,21 @@
 // two-thread partitions, y = p - 2), so n1 = n R13 / (2 R13 + p - 2) and
 // n3 = n / (2 R13 + p - 2).
 //
-// The reduced system is solved over a merge tree that works for any p:
-// at every level adjacent nodes are paired left to right and an odd last
-// node is carried up unchanged.  This gives p - 1 merges (one 2x2-block
-// interface system per partition interface, as the recursive-SPIKE section
-// counts) over ceil(log2 p) levels, and reduces to the paper's halving
-// recursion when p is a power of two.
+// The reduced system is solved over a merge tree.  The balanced tree works
+// for any p: at every level adjacent nodes are paired left to right and an
+// odd last node is carried up unchanged.  This gives p - 1 merges (one
+// 2x2-block interface system per partition interface, as the recursive-SPIKE
+// section counts) over ceil(log2 p) levels, and reduces to the paper's
+// halving recursion when p is a power of two.  The paper layout (flexible
+// thread distribution of the load-balancing section) takes p = 2^m + r
+// leaves: the r inner two-thread partitions, allocated in order from the
+// second partition, are leaf pairs (1,2), (3,4), ..., (2r-1,2r) that merge
+// first, and a complete binary tree then runs over the remaining 2^m nodes.
+// The first and last partitions stay single-threaded, so r <= 2^m - 2.
+//
+// With R13 sizing the two layouts give the same sizes: the paper's R12 =
+// R13/2 makes each half of a two-thread partition n2/2 = n3 rows long, and
+// 2 r + (2^m - 2 - r) = p - 2 inner leaves of n3 rows remain either way.
 #include "spike_plan.hpp"
 
 #include <algorithm>
@@ -32,6 +41,16 @@ void default_opts(spike_opts *o) {
   o->boost_tau = -1.0;
   o->max_refine = -1;
   o->refine_tol = 1e-13;
+  o->tree = 0;
+}
+
+// Paper tree layout: is p = 2^m + r with 0 <= r <= 2^m - 2?  Sets m2 = 2^m.
+static bool paper_tree_admissible(int p, int *m2) {
+  if (p < 1) return false;
+  int q = 1;
+  while (2 * q <= p) q *= 2;
+  if (m2) *m2 = q;
+  return p == q || p - q <= q - 2;
 }
 
 double ratio_r13(double K, double r) {
@@ -56,7 +75,8 @@ static int choose_p(int64_t n, int kl, int ku) {
 
 int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
   if (o.p < 0 || (o.pivot != 0 && o.pivot != 1) || (o.precision != 0 && o.precision != 1) ||
-      (o.sizing != 0 && o.sizing != 1) || o.nrhs_max < 0 || o.nrhs_hint < 0)
+      (o.sizing != 0 && o.sizing != 1) || (o.tree != 0 && o.tree != 1) || o.nrhs_max < 0 ||
+      o.nrhs_hint < 0)
     return -4;
   pl = Plan();
   pl.n = n;
@@ -79,6 +99,11 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
   int p = o.p > 0 ? o.p : choose_p(n, kl, ku);
   if (n == 0) p = 1;
   if (p > std::max<int64_t>(n, 1)) return -4;
+  int m2 = 1;
+  if (o.tree == 1 && !paper_tree_admissible(p, &m2)) {
+    if (o.p > 0) return -4;
+    p = 2 * m2 - 2;   // the largest admissible count below 2^(m+1) - 1
+  }
   pl.p = p;
 
   // ---- partition sizes
@@ -173,30 +198,39 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
     sscr += (int64_t)(pl.sscr_rows * R);
   }
 
-  // ---- merge tree
+  // ---- merge tree (a merged node takes id p + its interface index)
   struct Node { int a, b, id; };
   std::vector<Node> cur;
   for (int i = 0; i < p; ++i) cur.push_back({i, i, i});
   pl.level_off.assign(1, 0);
   int level = 0;
+  auto merge = [&](const Node &Lt, const Node &Rt) {
+    MergeDesc md{};
+    md.mif = Lt.b;
+    md.left = Lt.id;
+    md.right = Rt.id;
+    md.a = Lt.a;
+    md.b = Rt.b;
+    md.level = level;
+    pl.merges.push_back(md);
+    return Node{Lt.a, Rt.b, p + Lt.b};
+  };
+  if (o.tree == 1 && p > m2) {
+    // level 1: the halves of the r two-thread partitions
+    const int r = p - m2;
+    ++level;
+    std::vector<Node> nxt{cur[0]};
+    for (int j = 0; j < r; ++j) nxt.push_back(merge(cur[1 + 2 * j], cur[2 + 2 * j]));
+    for (int i = 2 * r + 1; i < p; ++i) nxt.push_back(cur[i]);
+    pl.level_off.push_back((int)pl.merges.size());
+    cur.swap(nxt);
+  }
   while (cur.size() > 1) {
     ++level;
     std::vector<Node> nxt;
     for (size_t i = 0; i < cur.size(); i += 2) {
-      if (i + 1 < cur.size()) {
-        const Node &Lt = cur[i], &Rt = cur[i + 1];
-        MergeDesc md{};
-        md.mif = Lt.b;
-        md.left = Lt.id;
-        md.right = Rt.id;
-        md.a = Lt.a;
-        md.b = Rt.b;
-        md.level = level;
-        pl.merges.push_back(md);
-        nxt.push_back({Lt.a, Rt.b, p + Lt.b});
-      } else {
-        nxt.push_back(cur[i]);
-      }
+      if (i + 1 < cur.size()) nxt.push_back(merge(cur[i], cur[i + 1]));
+      else nxt.push_back(cur[i]);
     }
     pl.level_off.push_back((int)pl.merges.size());
     cur.swap(nxt);

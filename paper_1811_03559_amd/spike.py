@@ -31,7 +31,8 @@ _c_p = ctypes.c_void_p
 class Opts(ctypes.Structure):
     _fields_ = [("p", _c_i32), ("pivot", _c_i32), ("precision", _c_i32), ("sizing", _c_i32),
                 ("K", _c_dbl), ("nrhs_hint", _c_i32), ("nrhs_max", _c_i32),
-                ("boost_tau", _c_dbl), ("max_refine", _c_i32), ("refine_tol", _c_dbl)]
+                ("boost_tau", _c_dbl), ("max_refine", _c_i32), ("refine_tol", _c_dbl),
+                ("tree", _c_i32)]
 
 
 class Status(ctypes.Structure):
@@ -98,6 +99,9 @@ def lib():
             L.spike_plan_query.restype = ctypes.c_int
             L.spike_plan_query.argtypes = [_c_i64, _c_i32, _c_i32, ctypes.POINTER(Opts),
                                            ctypes.POINTER(PlanInfo), ctypes.POINTER(_c_i64)]
+            L.spike_plan_tree.restype = ctypes.c_int
+            L.spike_plan_tree.argtypes = [_c_i64, _c_i32, _c_i32, ctypes.POINTER(Opts),
+                                          ctypes.POINTER(_c_i32)]
             L.spike_workspace_size.restype = ctypes.c_int
             L.spike_workspace_size.argtypes = [_c_i64, _c_i32, _c_i32, ctypes.POINTER(Opts),
                                                ctypes.POINTER(_c_size)]
@@ -183,7 +187,8 @@ def profile_report():
 
 
 def make_opts(p=0, pivot=False, precision="fp64", sizing="equal", K=0.0, nrhs_hint=0,
-              nrhs_max=64, boost_tau=-1.0, max_refine=-1, refine_tol=1e-13) -> Opts:
+              nrhs_max=64, boost_tau=-1.0, max_refine=-1, refine_tol=1e-13,
+              tree="balanced") -> Opts:
     o = Opts()
     lib().spike_default_opts(ctypes.byref(o))
     o.p = int(p)
@@ -196,6 +201,7 @@ def make_opts(p=0, pivot=False, precision="fp64", sizing="equal", K=0.0, nrhs_hi
     o.boost_tau = float(boost_tau)
     o.max_refine = int(max_refine)
     o.refine_tol = float(refine_tol)
+    o.tree = {"balanced": 0, "paper": 1, 0: 0, 1: 1}[tree]
     return o
 
 
@@ -212,6 +218,19 @@ def plan_query(n, kl, ku, **opts):
     return {"p": info.p, "levels": info.levels, "merges": info.merges,
             "reduced_size": info.reduced_size, "workspace_bytes": info.workspace_bytes,
             "sizes": [sizes[i] for i in range(info.p)]}
+
+
+def plan_tree(n, kl, ku, **opts):
+    """Host-only query of the merge tree: a list of (level, a, m, b) per
+    interface system in launch order; the merged node spans leaves a..b and
+    its children a..m and m+1..b."""
+    o = make_opts(**opts)
+    p = plan_query(n, kl, ku, **opts)["p"]
+    buf = (_c_i32 * max(1, 4 * (p - 1)))()
+    rc = lib().spike_plan_tree(int(n), int(kl), int(ku), ctypes.byref(o), buf)
+    if rc != 0:
+        raise SpikeError("spike_plan_tree", rc)
+    return [tuple(buf[4 * d:4 * d + 4]) for d in range(p - 1)]
 
 
 def workspace_size(n, kl, ku, **opts) -> int:
@@ -397,7 +416,7 @@ def autotune(ab, kl, ku, nrhs=1, stream=None, **base):
     r = res.opts
     opts = {"p": r.p, "pivot": bool(r.pivot), "precision": "mixed" if r.precision else "fp64",
             "sizing": "r13" if r.sizing else "equal", "K": r.K, "nrhs_hint": r.nrhs_hint,
-            "nrhs_max": r.nrhs_max}
+            "nrhs_max": r.nrhs_max, "tree": "paper" if r.tree else "balanced"}
     return opts, {"factor_ms": res.factor_ms, "solve_ms": res.solve_ms, "K": res.K,
                   "candidates": res.candidates}
 

@@ -30,13 +30,27 @@ def merge_tree(p):
     return merges, level
 
 
+def tree_from_spans(p, spans):
+    """Merge dicts from (level, a, m, b) tuples in launch order: the left child
+    spans leaves a..m and the right m+1..b.  A child must be a leaf or a node
+    an earlier merge formed (else KeyError)."""
+    owner = {(i, i): i for i in range(p)}
+    merges = []
+    for level, a, m, b in spans:
+        merges.append(dict(mif=m, left=owner[(a, m)], right=owner[(m + 1, b)], a=a, b=b, level=level))
+        owner[(a, b)] = p + m
+    return merges, max((s[0] for s in spans), default=0)
+
+
 class Model:
-    def __init__(self, A, sizes, kl, ku):
+    def __init__(self, A, sizes, kl, ku, tree=None):
+        """tree: (merges, levels) as merge_tree returns; the balanced tree by
+        default."""
         self.A, self.kl, self.ku = A, kl, ku
         self.sizes = list(sizes)
         self.p = p = len(sizes)
         self.starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(int)
-        self.merges, self.levels = merge_tree(p)
+        self.merges, self.levels = tree if tree is not None else merge_tree(p)
         self.tips = {}
         for i in range(p):
             s, m = self.starts[i], self.sizes[i]

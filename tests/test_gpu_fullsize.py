@@ -36,9 +36,11 @@ def _solve(dab, kl, ku, F, trans=False, **opts):
     return X, info
 
 
-@pytest.mark.parametrize("p", [256, 250, 500])
-def test_cfg1_full_size(p):
-    """n = 10^6, kl = ku = 160, nrhs = 1, N and T, manufactured solution."""
+@pytest.mark.parametrize("p,tree", [(256, "balanced"), (250, "balanced"), (500, "balanced"),
+                                    (250, "paper"), (500, "paper")])
+def test_cfg1_full_size(p, tree):
+    """n = 10^6, kl = ku = 160, nrhs = 1, N and T, manufactured solution; the
+    paper's tree layout at its 2^m + r counts 250 = 128 + 122, 500 = 256 + 244."""
     import torch
     n, k = 1_000_000, 160
     ab, kl, ku, Xt = inputs.cfg1(n=n, k=k, nrhs=1)
@@ -46,7 +48,7 @@ def test_cfg1_full_size(p):
     kappa = _kappa_inf_bound(ab, kl, ku)
     for trans in (False, True):
         F = oracle.gbmv(ab, kl, ku, Xt, trans=trans)
-        X, info = _solve(dab, kl, ku, F, trans=trans, p=p, nrhs_max=64)
+        X, info = _solve(dab, kl, ku, F, trans=trans, p=p, nrhs_max=64, tree=tree)
         assert info["info"] == 0 and info["n_boosts"] == 0
         rr = oracle.relres(ab, kl, ku, X, F, trans=trans)
         assert rr <= RELRES, (p, trans, rr)

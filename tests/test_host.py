@@ -29,6 +29,76 @@ def test_plan_tree_shape(p):
     assert sum(info["sizes"]) == 100_000
 
 
+def _paper_admissible(t):
+    """The load-balancing section's thread layout: t = 2^m + r threads, with
+    2^m <= t <= 2^(m+1) - 2 (the first and last partitions keep one thread),
+    so 7 threads are used as 6 and 15 as 14; one thread is plain LU."""
+    m = int(math.floor(math.log2(t)))
+    return t == 1 or 2 ** m <= t <= 2 ** (m + 1) - 2
+
+
+@pytest.mark.parametrize("p", range(1, 65))
+def test_paper_tree_admits_exactly_the_paper_thread_counts(p):
+    n = 600 * 64
+    if _paper_admissible(p):
+        info = spike.plan_query(n, 4, 4, p=p, tree="paper")
+        assert info["p"] == p and info["merges"] == p - 1
+        assert info["levels"] == (0 if p == 1 else math.ceil(math.log2(p)))
+    else:
+        with pytest.raises(spike.SpikeError) as e:
+            spike.plan_query(n, 4, 4, p=p, tree="paper")
+        assert e.value.code == -4
+        assert spike.plan_query(n, 4, 4, p=p)["p"] == p      # the balanced tree takes any p
+
+
+@pytest.mark.parametrize("t,used", [(7, 6), (15, 14), (6, 6), (3, 2)])
+def test_paper_tree_lowers_the_planners_count(t, used):
+    # kl = ku = 4: the planner's own count is n / 512
+    assert spike.plan_query(512 * t, 4, 4)["p"] == t
+    assert spike.plan_query(512 * t, 4, 4, tree="paper")["p"] == used
+
+
+@pytest.mark.parametrize("p", [2, 4, 5, 6, 12, 13, 14, 17, 250, 256, 500])
+def test_paper_tree_layout(p):
+    """Level 1 merges the halves of the r two-thread partitions, which sit at
+    the paper's partitions 2, 3, ..., r+1 (leaf pairs (1,2), (3,4), ... from
+    0); every later level pairs all 2^m remaining nodes with none carried."""
+    n, k = 1_000_000, 160
+    m2 = 2 ** int(math.floor(math.log2(p)))
+    r = p - m2
+    tree = spike.plan_tree(n, k, k, p=p, tree="paper")
+    assert len(tree) == p - 1
+    assert sorted(m for _, _, m, _ in tree) == list(range(p - 1))
+    lvl1 = [J for J in tree if J[0] == 1]
+    if r:
+        assert lvl1 == [(1, 2 * j - 1, 2 * j - 1, 2 * j) for j in range(1, r + 1)]
+    nodes = [(0, 0)] + [(2 * j - 1, 2 * j) for j in range(1, r + 1)] + [(i, i) for i in range(2 * r + 1, p)]
+    if not r:
+        nodes = [(i, i) for i in range(p)]
+    assert len(nodes) == m2
+    first = 2 if r else 1
+    for level in range(first, max(J[0] for J in tree) + 1):
+        got = [(a, m, b) for lv, a, m, b in tree if lv == level]
+        want = [(nodes[i][0], nodes[i][1], nodes[i + 1][1]) for i in range(0, len(nodes), 2)]
+        assert got == want, level
+        nodes = [(nodes[i][0], nodes[i + 1][1]) for i in range(0, len(nodes), 2)]
+    assert nodes == [(0, p - 1)]
+    # the paper's R12 = R13 / 2 gives every half of a two-thread partition
+    # the single-thread size n3, so both trees size the partitions alike
+    for sizing in ("equal", "r13"):
+        a = spike.plan_query(n, k, k, p=p, sizing=sizing, nrhs_hint=1)["sizes"]
+        b = spike.plan_query(n, k, k, p=p, sizing=sizing, nrhs_hint=1, tree="paper")["sizes"]
+        assert a == b
+
+
+def test_unknown_tree_is_an_error():
+    import ctypes
+    o = spike.make_opts()
+    o.tree = 2
+    info = spike.PlanInfo()
+    assert spike.lib().spike_plan_query(1000, 2, 2, ctypes.byref(o), ctypes.byref(info), None) == -4
+
+
 def test_cfg0_equal_sizes():
     info = spike.plan_query(4096, 4, 4, p=3)
     assert info["sizes"] == [1365, 1365, 1366]

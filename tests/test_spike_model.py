@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1811_03559_amd import inputs
-from spike_model import Model, merge_tree
+from spike_model import Model, merge_tree, tree_from_spans
 from test_oracle import dense_from_band
 
 
@@ -36,6 +36,25 @@ def test_model_solves_match_dense(p, kl, ku):
     _, A = dd_matrix(n, kl, ku, 1000 + 31 * p + 7 * kl + ku)
     F = inputs.rhs(n, 3, inputs.rng_for(9)).T
     M = Model(A, sizes_for(n, p), kl, ku)
+    np.testing.assert_allclose(M.solve(F), np.linalg.solve(A, F), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(M.solve_t(F), np.linalg.solve(A.T, F), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [5, 6, 9, 12, 14])
+@pytest.mark.parametrize("kl,ku", [(2, 3), (4, 4), (0, 2)])
+def test_model_solves_match_dense_over_the_planners_paper_tree(p, kl, ku):
+    """The merge tree the host planner builds for the paper's 2^m + r layout
+    (host query, no device) is a valid merge order for the SPIKE algebra:
+    every merge joins two nodes that exist, and the solves it gives match
+    dense solves."""
+    from paper_1811_03559_amd import spike
+    n = 16 * p + 5
+    _, A = dd_matrix(n, kl, ku, 2000 + 31 * p + 7 * kl + ku)
+    F = inputs.rhs(n, 3, inputs.rng_for(19)).T
+    sizes = spike.plan_query(n, kl, ku, p=p, tree="paper")["sizes"]
+    tree = tree_from_spans(p, spike.plan_tree(n, kl, ku, p=p, tree="paper"))
+    assert tree[0] != merge_tree(p)[0]                   # not the balanced tree
+    M = Model(A, sizes, kl, ku, tree=tree)
     np.testing.assert_allclose(M.solve(F), np.linalg.solve(A, F), rtol=1e-10, atol=1e-12)
     np.testing.assert_allclose(M.solve_t(F), np.linalg.solve(A.T, F), rtol=1e-10, atol=1e-12)
 
