@@ -9,6 +9,7 @@
 #include <climits>
 
 #include "spike_device.hpp"
+#include "spike_profile.hpp"
 #include "spike_refine.hpp"
 
 namespace spike {
@@ -23,34 +24,87 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
 
 __device__ __forceinline__ double from_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+// Band entries loaded ahead of their use, per thread and round.  A load
+// whose entry lies outside the band reads a stored entry of the same band
+// column instead and its value is replaced by zero, so the RU loads of a
+// round have no branches between them and are in flight together.
+constexpr int RU = 8;
+
+// Stored position of row i in band column j, clamped into the band.
+__device__ __forceinline__ int64_t band_pos(int64_t i, int64_t j, int64_t ldab, int kl, int ku) {
+  int64_t d = i - j;
+  d = d < -ku ? -ku : (d > kl ? kl : d);
+  return (ku + d) + j * ldab;
+}
+
+__device__ __forceinline__ double max_over_wave(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
 // ||A||_inf (row abs-sums) and ||A||_1 (column abs-sums) of the FP64 band.
+// Thread t of a workgroup sums row i0 + t over the band columns that touch
+// the workgroup's rows (the same column for all threads at a time, so the
+// loads are coalesced along it; a wavefront skips the columns that hold none
+// of its rows' entries) and column i0 + t over its band entries (one
+// contiguous run per thread).
 __global__ __launch_bounds__(RT) void k_anorm(const double* ab, int64_t ldab, int64_t n, int kl, int ku,
                                                DevStatus* st) {
   const int64_t i0 = (int64_t)blockIdx.x * RT;
   const int64_t i = i0 + threadIdx.x;
-  double rs = 0.0;
-  const int64_t jlo = i0 - kl > 0 ? i0 - kl : 0;
-  const int64_t jhi = i0 + RT + ku < n ? i0 + RT + ku : n;   // exclusive
-  for (int64_t j = jlo; j < jhi; ++j) {
-    int64_t d = i - j;
-    if (i < n && d <= kl && -d <= ku) rs += fabs(ab[(ku + d) + j * ldab]);
-  }
-  // column sums of columns [i0, i0 + RT): wave per column
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  double cmax = 0.0;
-  for (int64_t c = i0 + wave; c < i0 + RT && c < n; c += RT / 64) {
-    double cs = 0.0;
-    for (int s = lane; s < kl + ku + 1; s += 64) {
-      int64_t r = c + s - ku;
-      if (r >= 0 && r < n) cs += fabs(ab[s + c * ldab]);
+  const bool live = i < n;
+  double rs = 0.0, cs = 0.0;
+  const int64_t w0 = i0 + (threadIdx.x & ~63);
+  const int64_t jlo = w0 - kl > 0 ? w0 - kl : 0;
+  const int64_t jhi = w0 + 64 + ku < n ? w0 + 64 + ku : n;   // exclusive
+  for (int64_t j0 = jlo; j0 < jhi; j0 += RU) {
+    double a[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t j = j0 + u < jhi ? j0 + u : jhi - 1;
+      const int64_t d = i - j;
+      const bool in = live && j0 + u < jhi && d <= kl && -d <= ku;
+      a[u] = gld(ab + band_pos(i, j, ldab, kl, ku));
+      a[u] = in ? a[u] : 0.0;
     }
-    for (int off = 32; off > 0; off >>= 1) cs += __shfl_xor(cs, off);
-    cmax = fmax(cmax, cs);
+#pragma unroll
+    for (int u = 0; u < RU; ++u) rs += fabs(a[u]);
   }
-  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-  if (lane == 0) {
+  // column sums of the wavefront's 64 columns w0 .. w0 + 63, lanes over the
+  // stored rows s of a column (coalesced), CB columns' loads in flight
+  // together; each lane sums its rows in ascending order, then the
+  // wavefront's tree sum
+  constexpr int CB = 16;
+  const int wl = kl + ku + 1, lane = threadIdx.x & 63;
+  for (int c0 = 0; c0 < 64; c0 += CB) {
+    double part[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) part[cb] = 0.0;
+    for (int s0 = 0; s0 < wl; s0 += 64) {
+      const int sl = s0 + lane;
+      double a[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int64_t c = w0 + c0 + cb, r = c + sl - ku;
+        const bool in = c < n && sl < wl && r >= 0 && r < n;
+        const int64_t cc = c < n ? c : n - 1;
+        a[cb] = gld(ab + (sl < wl ? sl : wl - 1) + cc * ldab);
+        a[cb] = in ? a[cb] : 0.0;
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) part[cb] += fabs(a[cb]);
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      double v = part[cb];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      cs = fmax(cs, v);
+    }
+  }
+  rs = max_over_wave(rs);
+  if ((threadIdx.x & 63) == 0) {
     atomic_max_nonneg(&st->anorm_inf_bits, rs);
-    atomic_max_nonneg(&st->anorm_one_bits, cmax);
+    atomic_max_nonneg(&st->anorm_one_bits, cs);
   }
 }
 
@@ -77,69 +131,113 @@ __global__ __launch_bounds__(RT) void k_copy_cols(const double* S, int64_t lds, 
 }
 
 // Right-hand sides handled per pass over the band (accumulators per thread)
-// and band columns staged per LDS round.
+// by the transposed residual.
 constexpr int RQ = 16;
-constexpr int RJ = 64;
+
+// Lane `src` (wave-uniform) of v, for every lane: the value lands in scalar
+// registers, so the products that use it read no LDS.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
 
 // R = F - A X, plus per-column max |R| and max |X| (colred[2q], colred[2q+1]).
-// A workgroup owns RT consecutive rows; for every group of RQ right-hand
-// sides it walks the band columns touching those rows once (coalesced along
-// each column), with the matching RJ x RQ slice of X staged in LDS.  Each
-// row's sum runs over the columns in ascending order.
+// A wavefront owns 64 consecutive rows, a lane each; for every group of NQ
+// right-hand sides it walks the band columns touching its rows (coalesced
+// along each column) in rounds of 64, lane l holding row jb + l of the NQ
+// columns of X, which the products take lane by lane through scalar
+// registers.  RU band entries per lane are loaded before their products (an
+// entry outside the band reads the row's diagonal entry and enters as zero).
+// Each row's sum runs over the columns in ascending order.
+template <int NQ>
 __global__ __launch_bounds__(RT) void k_residual_n(const double* ab, int64_t ldab, int64_t n, int kl, int ku,
                                                     const double* F, const double* X, int64_t ldx, double* R,
                                                     int64_t ld, int nrhs, unsigned long long* colred,
                                                     const int32_t* skip) {
   if (*skip) return;
-  __shared__ double xs[RJ][RQ + 1];
-  const int64_t i0 = (int64_t)blockIdx.x * RT;
-  const int64_t i = i0 + threadIdx.x;
-  const int64_t jlo = i0 - kl > 0 ? i0 - kl : 0;
-  const int64_t jhi = i0 + RT + ku < n ? i0 + RT + ku : n;
-  const int lane = threadIdx.x % 64;
-  for (int q0 = 0; q0 < nrhs; q0 += RQ) {
-    const int nq = nrhs - q0 < RQ ? nrhs - q0 : RQ;
-    double acc[RQ];
+  __shared__ double red[2][RT / 64][NQ];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t w0 = (int64_t)blockIdx.x * RT + 64 * wave;
+  const int64_t i = w0 + lane;
+  const bool live = i < n;
+  const int64_t home = live ? ku + i * ldab : 0;   // stand-in address: the row's diagonal entry
+  // band columns [jlo, jhi) hold all entries of this wavefront's rows
+  const int64_t jlo = w0 - kl > 0 ? w0 - kl : 0;
+  const int64_t jhi = w0 + 64 + ku < n ? w0 + 64 + ku : n;
+  for (int q0 = 0; q0 < nrhs; q0 += NQ) {
+    const int nq = nrhs - q0 < NQ ? nrhs - q0 : NQ;
+    double acc[NQ];
 #pragma unroll
-    for (int t = 0; t < RQ; ++t) acc[t] = 0.0;
-    for (int64_t jb = jlo; jb < jhi; jb += RJ) {
-      const int nj = jhi - jb < RJ ? (int)(jhi - jb) : RJ;
-      __syncthreads();
-      for (int e = threadIdx.x; e < RJ * RQ; e += RT) {
-        const int jj = e % RJ, t = e / RJ;
-        xs[jj][t] = (jj < nj && t < nq) ? X[(jb + jj) + (int64_t)(q0 + t) * ldx] : 0.0;
+    for (int t = 0; t < NQ; ++t) acc[t] = 0.0;
+    for (int64_t jb = jlo; jb < jhi; jb += 64) {
+      const int nj = jhi - jb < 64 ? (int)(jhi - jb) : 64;
+      double xv[NQ];
+#pragma unroll
+      for (int t = 0; t < NQ; ++t) {
+        const bool ok = lane < nj && t < nq;
+        xv[t] = gld(X + (ok ? (jb + lane) + (int64_t)(q0 + t) * ldx : 0));
+        xv[t] = ok ? xv[t] : 0.0;
       }
-      __syncthreads();
-      for (int jj = 0; jj < nj; ++jj) {
-        const int64_t j = jb + jj;
-        const int64_t d = i - j;
-        if (i < n && d <= kl && -d <= ku) {
-          const double a = ab[(ku + d) + j * ldab];
+      for (int jj0 = 0; jj0 < nj; jj0 += RU) {
+        double a[RU];
 #pragma unroll
-          for (int t = 0; t < RQ; ++t) acc[t] = fma(a, xs[jj][t], acc[t]);
+        for (int u = 0; u < RU; ++u) {
+          const int64_t j = jb + jj0 + u;
+          const int64_t d = i - j;
+          const bool in = live && jj0 + u < nj && d <= kl && -d <= ku;
+          a[u] = gld(ab + (in ? (ku + d) + j * ldab : home));
+          a[u] = in ? a[u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+#pragma unroll
+          for (int t = 0; t < NQ; ++t) acc[t] = fma(a[u], lane_value(xv[t], jj0 + u), acc[t]);
         }
       }
     }
+    // R = F - A X and the per-column maxima, reduced over the workgroup
 #pragma unroll
-    for (int t = 0; t < RQ; ++t) {
-      if (t >= nq) break;
-      const int q = q0 + t;
-      double r = 0.0, xa = 0.0;
-      if (i < n) {
-        r = F[i + (int64_t)q * ld] - acc[t];
-        R[i + (int64_t)q * ld] = r;
-        xa = fabs(X[i + (int64_t)q * ldx]);
+    for (int t0 = 0; t0 < NQ; t0 += 8) {
+      constexpr int G = NQ < 8 ? NQ : 8;
+      double f[G], x[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int t = t0 + g;
+        const bool ok = live && t < nq;
+        const int64_t q = q0 + (ok ? t : 0);
+        f[g] = gld(F + (ok ? i + q * ld : 0));
+        x[g] = gld(X + (ok ? i + q * ldx : 0));
       }
-      double ra = fabs(r);
-      for (int off = 32; off > 0; off >>= 1) {
-        ra = fmax(ra, __shfl_xor(ra, off));
-        xa = fmax(xa, __shfl_xor(xa, off));
-      }
-      if (lane == 0) {
-        atomic_max_nonneg(&colred[2 * q], ra);
-        atomic_max_nonneg(&colred[2 * q + 1], xa);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int t = t0 + g;
+        double ra = 0.0, xa = 0.0;
+        if (live && t < nq) {
+          const double r = f[g] - acc[t];
+          gst(R + i + (int64_t)(q0 + t) * ld, r);
+          ra = fabs(r);
+          xa = fabs(x[g]);
+        }
+        ra = max_over_wave(ra);
+        xa = max_over_wave(xa);
+        if (lane == 0) {
+          red[0][wave][t] = ra;
+          red[1][wave][t] = xa;
+        }
       }
     }
+    __syncthreads();
+    if (tid < 2 * nq) {
+      const int which = tid / nq, t = tid % nq;
+      double m = red[which][0][t];
+#pragma unroll
+      for (int w = 1; w < RT / 64; ++w) m = fmax(m, red[which][w][t]);
+      atomic_max_nonneg(&colred[2 * (q0 + t) + which], m);
+    }
+    __syncthreads();   // red is rewritten by the next group
   }
 }
 
@@ -224,7 +322,11 @@ int chk() {
 
 int prepare_refine(const KParams& k, const Plan& pl, char*, hipStream_t st) {
   int64_t blocks = (pl.n + RT - 1) / RT;
-  hipLaunchKernelGGL(k_anorm, dim3((unsigned)blocks), dim3(RT), 0, st, k.dAB, k.ldab, pl.n, pl.kl, pl.ku, k.status);
+  {
+    ProfScope ps("k_anorm", st);
+    hipLaunchKernelGGL(k_anorm, dim3((unsigned)blocks), dim3(RT), 0, st, k.dAB, k.ldab, pl.n, pl.kl, pl.ku,
+                       k.status);
+  }
   if (int e = chk()) return e;
   hipLaunchKernelGGL(k_refine_activate, dim3(1), dim3(64), 0, st, k.status);
   return chk();
@@ -241,7 +343,10 @@ int refined_solve(const KParams& k, const LaunchCfg& c, const Plan& pl, char* ws
   if (grid > 65535u * 4u) grid = 65535u * 4u;
   hipLaunchKernelGGL(k_refine_begin, dim3(1), dim3(64), 0, st, k.status, colred, nrhs);
   if (int e = chk()) return e;
-  hipLaunchKernelGGL(k_copy_cols, dim3(grid), dim3(RT), 0, st, B, ldb, Fc, n, n, nrhs, skip);
+  {
+    ProfScope ps("k_copy_cols", st);
+    hipLaunchKernelGGL(k_copy_cols, dim3(grid), dim3(RT), 0, st, B, ldb, Fc, n, n, nrhs, skip);
+  }
   if (int e = chk()) return e;
   if (int e = launch_solve(k, c, st, B, ldb, nrhs, trans)) return e;
   KParams kr = k;
@@ -249,19 +354,35 @@ int refined_solve(const KParams& k, const LaunchCfg& c, const Plan& pl, char* ws
   const unsigned rblocks_n = (unsigned)((n + RT - 1) / RT);
   const unsigned rblocks_t = (unsigned)((n + RT / 64 - 1) / (RT / 64));
   for (int it = 0; it <= pl.max_refine; ++it) {
-    if (!trans)
-      hipLaunchKernelGGL(k_residual_n, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc, B,
-                         ldb, Rr, n, nrhs, colred, skip);
-    else
+    if (!trans) {
+      ProfScope ps("k_residual_n", st);
+      if (nrhs == 1)
+        hipLaunchKernelGGL(k_residual_n<1>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
+                           B, ldb, Rr, n, nrhs, colred, skip);
+      else if (nrhs <= 8)
+        hipLaunchKernelGGL(k_residual_n<8>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
+                           B, ldb, Rr, n, nrhs, colred, skip);
+      else if (nrhs <= 16)
+        hipLaunchKernelGGL(k_residual_n<16>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
+                           B, ldb, Rr, n, nrhs, colred, skip);
+      else
+        hipLaunchKernelGGL(k_residual_n<32>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
+                           B, ldb, Rr, n, nrhs, colred, skip);
+    } else {
+      ProfScope ps("k_residual_t", st);
       hipLaunchKernelGGL(k_residual_t, dim3(rblocks_t), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc, B,
                          ldb, Rr, n, nrhs, colred, skip);
+    }
     if (int e = chk()) return e;
     hipLaunchKernelGGL(k_berr, dim3(1), dim3(64), 0, st, k.status, colred, nrhs, trans ? 1 : 0, pl.refine_tol, it,
                        pl.max_refine);
     if (int e = chk()) return e;
     if (it == pl.max_refine) break;
     if (int e = launch_solve(kr, c, st, Rr, n, nrhs, trans)) return e;
-    hipLaunchKernelGGL(k_axpy_cols, dim3(grid), dim3(RT), 0, st, B, ldb, Rr, n, n, nrhs, skip);
+    {
+      ProfScope ps("k_axpy_cols", st);
+      hipLaunchKernelGGL(k_axpy_cols, dim3(grid), dim3(RT), 0, st, B, ldb, Rr, n, n, nrhs, skip);
+    }
     if (int e = chk()) return e;
   }
   return 0;
