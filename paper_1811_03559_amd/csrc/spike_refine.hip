@@ -339,8 +339,10 @@ int refined_solve(const KParams& k, const LaunchCfg& c, const Plan& pl, char* ws
   double* Rr = reinterpret_cast<double*>(ws + pl.off_res);
   auto* colred = reinterpret_cast<unsigned long long*>(ws + pl.off_colred);
   const int32_t* skip = &k.status->skip;
+  // the elementwise kernels stride over the grid; 4096 workgroups keep HBM
+  // busy and keep the launches that find the loop finished short
   unsigned grid = (unsigned)((n * nrhs + RT - 1) / RT);
-  if (grid > 65535u * 4u) grid = 65535u * 4u;
+  if (grid > 4096u) grid = 4096u;
   hipLaunchKernelGGL(k_refine_begin, dim3(1), dim3(64), 0, st, k.status, colred, nrhs);
   if (int e = chk()) return e;
   {

@@ -169,6 +169,24 @@ def test_mixed_precision_refinement(trans, pivot):
     check(ab, k, k, F, X, trans=trans, pivot=pivot, X_true=X_true)
 
 
+@pytest.mark.parametrize("nrhs", [1, 5, 17, 40])
+@pytest.mark.parametrize("trans", [False, True])
+def test_refinement_residual_right_hand_side_counts(nrhs, trans):
+    """FP64 refinement over ragged row counts (not a multiple of 64) and
+    every residual width: 1, <= 8, <= 32 (17: a partial group) and more
+    than one group of 32 (40); the refined solution must meet the bars and
+    the backward error the tolerance."""
+    n, k, p = 9001, 24, 6
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(inputs.seed_for(3) + nrhs),
+                              diag_mult_range=(1.01, 1.5))
+    X_true = inputs.rhs(n, nrhs, inputs.rng_for(40 + nrhs))
+    F = oracle.gbmv(ab, k, k, X_true, trans=trans)
+    X, info, _ = run(ab, k, k, F, trans=trans, p=p, precision="mixed", nrhs_max=64)
+    assert 1 <= info["refine_iters"] <= 6, info
+    assert 0 <= info["berr"] <= 1e-13, info
+    check(ab, k, k, F, X, trans=trans, pivot=False, X_true=X_true)
+
+
 def test_repeat_solve_is_bitwise_deterministic():
     import torch
     from paper_1811_03559_amd import spike
