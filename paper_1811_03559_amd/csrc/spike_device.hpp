@@ -57,6 +57,19 @@ __device__ __forceinline__ void sst(T* p, T v) {
 constexpr int NT = 256;      // threads per workgroup of the leaf and merge kernels
 constexpr int NWAVE = NT / 64;
 
+// Logical index of workgroup b of a G-workgroup launch such that the
+// workgroups of consecutive logical indices run on one XCD: workgroups are
+// handed to the XCDs round-robin (b mod NXCD), and XCD x takes the logical
+// range that starts after those of XCDs 0 .. x-1.  Workgroups that read the
+// same operands (the column groups of one partition, the tiles of one
+// merge) then share an L2.  A bijection of [0, G) for any G.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_grouped(int b, int G) {
+  const int x = b % NXCD, s = b / NXCD, q = G / NXCD, r = G % NXCD;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
+
 // Band storage: element (i, c), 0-based, at a[(kuw + i - c) + c * ldw],
 // for -kuw <= i - c <= kl.  With partial pivoting kuw = kl + ku (U fill).
 //

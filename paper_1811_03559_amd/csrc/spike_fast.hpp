@@ -85,18 +85,6 @@ __global__ __launch_bounds__(NT) void k_diag_inv(KParams k) {
 // the retrieval stage and take their single tip, the bottom klf rows of
 // U^{-1} L^{-1}[0; B'], from the trailing block of U from the 16-aligned row
 // ju <= m - klf.
-// Logical index of workgroup b of a G-workgroup launch such that the
-// workgroups of consecutive logical indices run on one XCD: workgroups are
-// handed to the XCDs round-robin (b mod NXCD), and XCD x takes the logical
-// range that starts after those of XCDs 0 .. x-1.  The column groups of one
-// partition, which all stream the same band factor, then share an L2.  A
-// bijection of [0, G) for any G.
-constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_grouped(int b, int G) {
-  const int x = b % NXCD, s = b / NXCD, q = G / NXCD, r = G % NXCD;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
-}
-
 template <typename T, int HT>
 __global__ __launch_bounds__(NT) void k_ftip_v(KParams k, int ncg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj, int 
   __shared__ double As[2][FG_KC * FG_PAD];   // As[kk][i]
   __shared__ double Bs[2][FG_KC * FG_PAD];   // Bs[kk][j]
   constexpr int NJ = fjobs(PH);
-  const int tile = blockIdx.x % tpj, rest = blockIdx.x / tpj;
+  const int b = xcd_grouped(blockIdx.x, gridDim.x);
+  const int tile = b % tpj, rest = b / tpj;
   const int job = rest % NJ, mm = rest / NJ;
   const MergeDesc J = k.merges[mbeg + mm];
   const FJob g = fused_job(k, J, PH, job);
@@ -595,13 +596,14 @@ __host__ __device__ constexpr int mtrsm_lds_elems() {
   return tile_lds_elems(HT);
 }
 
-// blockIdx.x = (merge * 2 + job) * ncg + cg; job 0: beta = S^{-1} V_t(R),
+// logical workgroup (merge * 2 + job) * ncg + cg; job 0: beta = S^{-1} V_t(R),
 // job 1: delta = S^{-1} Dm; columns [64 cg, 64 cg + 64).
 template <int HT>
 __global__ __launch_bounds__(NT) void k_mtrsm(KParams k, int mbeg, int ncg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  const int cg = blockIdx.x % ncg, rest = blockIdx.x / ncg;
+  const int b = xcd_grouped(blockIdx.x, gridDim.x);
+  const int cg = b % ncg, rest = b / ncg;
   const int job = rest % 2, mm = rest / 2;
   const MergeDesc J = k.merges[mbeg + mm];
   const int kl = k.kl, ku = k.ku, kw = k.kw, mi = J.mif;
