@@ -63,7 +63,24 @@ constexpr int NWAVE = NT / 64;
 // range that starts after those of XCDs 0 .. x-1.  Workgroups that read the
 // same operands (the column groups of one partition, the tiles of one
 // merge) then share an L2.  A bijection of [0, G) for any G.
+// Zeros in global memory, never written: the address that loads of entries
+// outside the stored data read instead, so that such loads need neither a
+// branch nor a select on their value (both would pull the wait for a
+// prefetched load to the point of issue).
+__device__ double kZeroEntries[2] = {0.0, 0.0};
+template <typename T>
+__device__ __forceinline__ const T* zero_entry() {
+  return reinterpret_cast<const T*>(kZeroEntries);
+}
+
 constexpr int NXCD = 8;
+
+// Workgroup barrier that waits only for this wavefront's LDS (and scalar
+// memory) operations.  __syncthreads() also waits for every global load in
+// flight, which would pull loads issued for later steps onto each step's
+// chain.  Only for loops whose threads exchange data through LDS alone; the
+// memory clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 __device__ __forceinline__ int xcd_grouped(int b, int G) {
   const int x = b % NXCD, s = b / NXCD, q = G / NXCD, r = G % NXCD;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;

@@ -56,9 +56,9 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
 
   int pos = tid;   // ring position of this thread's row (step 0 holds positions 0 .. RS-1)
   T rhs = T(0), upd = T(0);
-  if (act && pos < mp) {
+  {
     const int i = row_of(pos);
-    if (i < m) rhs = (T)src.load(i, 0);
+    rhs = (T)src.load_always(i, 0, act && pos < mp && i < m);
   }
 
   // coefficients M(i, 16 b + c), c = 0..15, of this thread's row at step sp;
@@ -72,12 +72,13 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     // valid c: FWD d = i - 16 b - c <= reach; BWD d = 16 b + c - i <= reach, 16 b + c < m
     const int clo = FWD ? i - 16 * b - reach : 0;
     const int chi = FWD ? 15 : min(reach + i - 16 * b, m - 1 - 16 * b);
+    // every load is issued (entries outside the band read a global zero),
+    // so neither a branch nor a select touches them before their use
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int cc = 16 * b + c;
-      T v = T(0);
-      if (ok && c >= clo && c <= chi) v = TRANS ? A.gl(cc, i) : A.gl(i, cc);
-      cf[c] = v;
+      const bool in = ok && c >= clo && c <= chi;
+      cf[c] = gld(in ? (TRANS ? &A.at(cc, i) : &A.at(i, cc)) : zero_entry<T>());
     }
   };
   // entries (r16, 4 g4 + c4) of the inverse of the diagonal block of step sp
@@ -117,9 +118,8 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
       const int e = tid + NT * u, q = e >> 4, c = e & 15;
       const int pp = 16 * sp + 16 + q, i = row_of(pp), cc = 16 * b + c;
       const int d = FWD ? i - cc : cc - i;
-      T v = T(0);
-      if (q < NQ && sp < nb && pp < mp && i < m && cc < m && d >= 1 && d <= reach) v = A.gl(cc, i);
-      r[u] = v;
+      const bool in = q < NQ && sp < nb && pp < mp && i < m && cc < m && d >= 1 && d <= reach;
+      r[u] = gld(in ? &A.at(cc, i) : zero_entry<T>());
     }
   };
   auto stage_store = [&](int sp, const T (&r)[CPT]) __attribute__((always_inline)) {
@@ -141,7 +141,10 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     T* wb = lds + (s & 1) * 16;
     const bool cur = act && pos < 16 * s + 16;
     if (cur) sst(wb + row_of(pos) - 16 * b, rhs - upd);
-    __syncthreads();
+    // threads exchange only LDS data within the sweep (each row's right-hand
+    // side is read by the thread that later publishes it, before it is
+    // stored), so the prefetches of later steps stay in flight
+    lds_barrier();
     // x = D_b^{-1} w_b; lane holds x of row 16 b + r16
     T xp = T(0);
 #pragma unroll
@@ -167,14 +170,14 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
       for (int c = 0; c < 16; ++c) a4[c & 3] += cv[c] * xs[c];
       upd += (a4[0] + a4[1]) + (a4[2] + a4[3]);
     }
-    if (cur) {
-      pos += RS;
-      upd = T(0);
-      rhs = T(0);
-      if (pos < mp) {
-        const int i = row_of(pos);
-        if (i < m) rhs = (T)src.load(i, 0);
-      }
+    {
+      // the current block's threads move to the rows entering the ring; every
+      // thread then (re)loads its row's right-hand side, so the load needs no
+      // select and is first used a step later
+      pos = cur ? pos + RS : pos;
+      upd = cur ? T(0) : upd;
+      const int i = row_of(pos);
+      rhs = (T)src.load_always(i, 0, act && pos < mp && i < m);
     }
     if constexpr (TRANS) {
       // step s + 1's coefficients (loaded NS - 1 steps ago) into the other

@@ -215,6 +215,15 @@ struct TSrc {
     int64_t o = (int64_t)r * rs + (int64_t)c * ld;
     return f64 ? gld(static_cast<const double*>(p) + o) : (double)gld(static_cast<const float*>(p) + o);
   }
+  // load(r, c) when `want`, else 0, with the load issued either way (from a
+  // global zero when the entry is not wanted or outside the source), so that
+  // neither a branch nor a select touches it before its use
+  __device__ __forceinline__ double load_always(int r, int c, bool want) const {
+    const bool ok = want && ((r >= lo1 && r < hi1) || (r >= lo2 && r < hi2)) && (c >= csplit || r >= clo);
+    const int64_t o = (int64_t)r * rs + (int64_t)c * ld;
+    if (f64) return gld(ok ? static_cast<const double*>(p) + o : zero_entry<double>());
+    return (double)gld(ok ? static_cast<const float*>(p) + o : zero_entry<float>());
+  }
 };
 
 // Destination of the solved rows: rows [0, top) go to p1 + r*rs, rows
