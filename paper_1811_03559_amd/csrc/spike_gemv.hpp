@@ -190,12 +190,20 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     }
     fetch_dv(s + NS, dvs);
   };
-  for (int s0 = 0; s0 < nb; s0 += NS) {
+  // whole groups of NS steps in the loop, so that every path around it
+  // issues the same loads and the waits for prefetched data stay exact;
+  // the last partial group after it
+  int s0 = 0;
+  for (; s0 + NS <= nb; s0 += NS) {
     static_for<0, NS>([&](auto D) __attribute__((always_inline)) {
       constexpr int d = decltype(D)::value;
-      if (s0 + d < nb) step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS]);
+      step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS]);
     });
   }
+  static_for<0, NS>([&](auto D) __attribute__((always_inline)) {
+    constexpr int d = decltype(D)::value;
+    if (s0 + d < nb) step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS]);
+  });
   __syncthreads();   // the last block's LDS reads before the caller reuses LDS
 }
 
