@@ -55,11 +55,7 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
   auto blk_of = [&](int s) { return FWD ? s : nb - 1 - s; };
 
   int pos = tid;   // ring position of this thread's row (step 0 holds positions 0 .. RS-1)
-  T rhs = T(0), upd = T(0);
-  {
-    const int i = row_of(pos);
-    rhs = (T)src.load_always(i, 0, act && pos < mp && i < m);
-  }
+  T upd = T(0);
 
   // coefficients M(i, 16 b + c), c = 0..15, of this thread's row at step sp;
   // the ring keeps every row strictly past the block (distance d >= 1), so
@@ -97,10 +93,16 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
   constexpr int NS = PD + 1;
   T cf[NS][16];
   T dv[NS][4];
+  // right-hand side of this thread's row, one copy per ring slot: a thread
+  // moves to a new row at most once in HT + 1 >= NS steps, so the copy
+  // loaded NS steps before a use holds the row it publishes
+  T rv[NS];
 #pragma unroll
   for (int d = 0; d < NS; ++d) {
     if constexpr (!TRANS) fetch_cf(d, cf[d]);
     fetch_dv(d, dv[d]);
+    const int i = row_of(pos);
+    rv[d] = (T)src.load_always(i, 0, act && pos < mp && i < m);
   }
 
   // transposed operators: cooperative loads of the coefficients of step sp
@@ -136,7 +138,7 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     stage_store(0, stg[0]);   // made visible by the first step's barrier
   }
 
-  auto step = [&](int s, T (&cfs)[16], T (&dvs)[4], T (&stg_s)[CPT], T (&stg_n)[CPT]) __attribute__((always_inline)) {
+  auto step = [&](int s, T (&cfs)[16], T (&dvs)[4], T (&stg_s)[CPT], T (&stg_n)[CPT], T& rhs) __attribute__((always_inline)) {
     const int b = blk_of(s);
     T* wb = lds + (s & 1) * 16;
     const bool cur = act && pos < 16 * s + 16;
@@ -172,8 +174,8 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
     }
     {
       // the current block's threads move to the rows entering the ring; every
-      // thread then (re)loads its row's right-hand side, so the load needs no
-      // select and is first used a step later
+      // thread then reloads its row's right-hand side into this slot's copy,
+      // so the load needs no select and is first used NS steps later
       pos = cur ? pos + RS : pos;
       upd = cur ? T(0) : upd;
       const int i = row_of(pos);
@@ -197,12 +199,12 @@ __device__ void gemv_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
   for (; s0 + NS <= nb; s0 += NS) {
     static_for<0, NS>([&](auto D) __attribute__((always_inline)) {
       constexpr int d = decltype(D)::value;
-      step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS]);
+      step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS], rv[d]);
     });
   }
   static_for<0, NS>([&](auto D) __attribute__((always_inline)) {
     constexpr int d = decltype(D)::value;
-    if (s0 + d < nb) step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS]);
+    if (s0 + d < nb) step(s0 + d, cf[d], dv[d], stg[d], stg[(d + 1) % NS], rv[d]);
   });
   __syncthreads();   // the last block's LDS reads before the caller reuses LDS
 }
