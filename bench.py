@@ -280,7 +280,9 @@ def bench_p_sweep(dab, ab, k, F, ps=(250, 500)):
 def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
     """Pivoting SPIKE next to non-pivoting SPIKE (with boosting) on the
     ill-conditioned N(0,1) row-scaled band: errors against the manufactured
-    solution, residuals, and FP64 refinement (<= 3 steps, same factors)."""
+    solution, residuals, FP64 refinement of the pivoting factors (<= 3
+    steps), and the boosted non-pivoting factors used as a preconditioner
+    for FP64 refinement (<= 10 steps)."""
     import torch
     from paper_1811_03559_amd import inputs, spike
     ab, kl, ku, Xtrue = inputs.cfg2(n=n, k=k, nrhs=nrhs)
@@ -291,7 +293,8 @@ def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
     for p in ps:
         row = {}
         for label, opts in (("pivoting", dict(pivot=True)), ("non_pivoting", dict(pivot=False)),
-                            ("pivoting_refined", dict(pivot=True, max_refine=3))):
+                            ("pivoting_refined", dict(pivot=True, max_refine=3)),
+                            ("boosted_refined", dict(pivot=False, max_refine=10))):
             holder = {}
 
             def fac():
@@ -305,7 +308,7 @@ def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
             row[label] = {"factor_ms": t_f, "solve_ms": t_s,
                           "relres": max(relres(ab, kl, ku, X[j], F[j]) for j in range(0, nrhs, 5)),
                           "fwd_err": fwd_err(X, Xtrue), "n_boosts": info["n_boosts"],
-                          "refine_iters": info["refine_iters"], "info": info["info"]}
+                          "refine_iters": info["refine_iters"], "berr": info["berr"], "info": info["info"]}
             f.close()
         out["p%d" % p] = row
     return out

@@ -80,8 +80,11 @@ typedef struct spike_opts {
                            refinement) with precision 0.  A positive value
                            with precision 0 refines every solve (useful
                            after boosted pivots or for ill-conditioned A,
-                           where SPIKE loses accuracy).  Refinement needs
-                           the caller's dAB to stay valid                [-1]    */
+                           where SPIKE loses accuracy).  Refinement stops
+                           at refine_tol, at the cap, on a non-finite
+                           residual, or when the backward error fails to
+                           halve in an iteration.  Refinement needs the
+                           caller's dAB to stay valid                    [-1]    */
     double refine_tol;  /* backward-error target of refinement        [1e-13]    */
     int32_t tree;       /* shape of the reduced-system merge tree:
                            0 = balanced: at every level adjacent nodes

@@ -282,10 +282,15 @@ __global__ __launch_bounds__(RT) void k_residual_t(const double* ab, int64_t lda
   }
 }
 
-// Backward error and the stopping decision of iteration `it`.
+// Backward error and the stopping decision of iteration `it`: stop at the
+// target, at the cap, on a non-finite residual, or when the backward error
+// failed to halve since the previous iteration (the stopping rule of
+// LAPACK's refinement routines: further corrections no longer pay, and on
+// factors far from A, such as heavily boosted ones, they diverge).
 __global__ void k_berr(DevStatus* st, unsigned long long* colred, int nrhs, int trans, double tol, int it,
                        int max_refine) {
   if (threadIdx.x != 0 || st->skip) return;
+  const double prev = st->berr;   // previous iteration's, or -1
   const double an = from_bits(trans ? st->anorm_one_bits : st->anorm_inf_bits);
   double berr = 0.0;
   bool finite = true;
@@ -300,7 +305,8 @@ __global__ void k_berr(DevStatus* st, unsigned long long* colred, int nrhs, int 
   // a non-finite residual or solution is reported as NaN and ends the loop
   if (!finite) berr = __builtin_nan("");
   st->berr = berr;
-  if (!finite || berr <= tol || it >= max_refine) st->skip = 1;
+  const bool stalled = it > 0 && prev >= 0.0 && !(berr <= 0.5 * prev);
+  if (!finite || berr <= tol || it >= max_refine || stalled) st->skip = 1;
   else st->refine_iters = it + 1;
 }
 
