@@ -17,7 +17,9 @@
  *   - only spike tips are formed, with truncated sweeps (Table tab:sweeps);
  *   - the reduced system is solved recursively, S^[l] = D^[l] S^[l+1]
  *     (section "Recursive reduced system", eqs. RED_SYS_RECA/RED_SYS_RECB,
- *     D1Inverse, S2Inverse), here over a merge tree valid for any p;
+ *     D1Inverse, S2Inverse), here over a balanced merge tree valid for any
+ *     p, or over the layout of the flexible thread distribution (section
+ *     "Load balancing") for its admissible p = 2^m + r;
  *   - the transpose solve reuses the same factorisation,
  *     A^T = S^T D^T (section "Transpose solve option", eqs. gform1/gform2,
  *     ATF, sweeps_in_D, transred1/transred2).

@@ -13,10 +13,13 @@
 //   3. every other thread subtracts its row of the coupling block times x
 //      (16 coefficients, prefetched PD steps ahead);
 //   4. the 16 threads of the current block move to the rows entering the
-//      ring and start their loads of those rows' right-hand side; a row's
-//      right-hand side is only combined with its accumulated update when the
-//      row becomes current, HT steps later, so no load latency lies on the
-//      chain of block steps.
+//      ring, and every thread reloads its row's right-hand side into the copy
+//      of this step's prefetch slot; a row's right-hand side is only combined
+//      with its accumulated update when the row becomes current, so no load
+//      latency lies on the chain of block steps.
+// The step barrier waits for LDS operations only, so the loads issued for
+// later steps stay in flight across it, and every load is issued without a
+// branch (entries outside the stored data read a global zero).
 // For U^T and L^T a row's 16 coefficients lie along one band column, so a
 // thread reading its own row would touch a different cache line in every
 // lane.  There the coefficients of a step are loaded cooperatively (16
