@@ -18,8 +18,8 @@
  *   - the reduced system is solved recursively, S^[l] = D^[l] S^[l+1]
  *     (section "Recursive reduced system", eqs. RED_SYS_RECA/RED_SYS_RECB,
  *     D1Inverse, S2Inverse), here over a balanced merge tree valid for any
- *     p, or over the layout of the flexible thread distribution (section
- *     "Load balancing") for its admissible p = 2^m + r;
+ *     p, or over the thread distribution of section "Flexible partitioning
+ *     scheme for recursive SPIKE" for its admissible p = 2^m + r;
  *   - the transpose solve reuses the same factorisation,
  *     A^T = S^T D^T (section "Transpose solve option", eqs. gform1/gform2,
  *     ATF, sweeps_in_D, transred1/transred2).
@@ -93,7 +93,8 @@ typedef struct spike_opts {
                            pair left to right, an odd last node carries
                            up; any p.
                            1 = the paper's flexible-threading layout
-                           (load-balancing section): p = 2^m + r leaves
+                           (distribution of threads, flexible
+                           partitioning section): p = 2^m + r leaves
                            with 0 <= r <= 2^m - 2; leaves 1..2r (0-based)
                            are the halves of r inner two-thread
                            partitions, placed from the second partition

@@ -11,11 +11,12 @@
 // odd last node is carried up unchanged.  This gives p - 1 merges (one
 // 2x2-block interface system per partition interface, as the recursive-SPIKE
 // section counts) over ceil(log2 p) levels, and reduces to the paper's
-// halving recursion when p is a power of two.  The paper layout (flexible
-// thread distribution of the load-balancing section) takes p = 2^m + r
-// leaves: the r inner two-thread partitions, allocated in order from the
-// second partition, are leaf pairs (1,2), (3,4), ..., (2r-1,2r) that merge
-// first, and a complete binary tree then runs over the remaining 2^m nodes.
+// halving recursion when p is a power of two.  The paper layout (the
+// distribution of threads of the flexible partitioning section) takes
+// p = 2^m + r leaves: the r inner two-thread partitions, allocated in order
+// from the second partition, are leaf pairs (1,2), (3,4), ..., (2r-1,2r)
+// that merge first, and a complete binary tree then runs over the remaining
+// 2^m nodes.
 // The first and last partitions stay single-threaded, so r <= 2^m - 2.
 //
 // With R13 sizing the two layouts give the same sizes: the paper's R12 =

@@ -30,8 +30,9 @@ def test_plan_tree_shape(p):
 
 
 def _paper_admissible(t):
-    """The load-balancing section's thread layout: t = 2^m + r threads, with
-    2^m <= t <= 2^(m+1) - 2 (the first and last partitions keep one thread),
+    """The flexible partitioning section's distribution of threads:
+    t = 2^m + r threads, with 2^m <= t <= 2^(m+1) - 2 (the first and last
+    partitions keep one thread),
     so 7 threads are used as 6 and 15 as 14; one thread is plain LU."""
     m = int(math.floor(math.log2(t)))
     return t == 1 or 2 ** m <= t <= 2 ** (m + 1) - 2
