@@ -189,6 +189,9 @@ def profile_report():
 def make_opts(p=0, pivot=False, precision="fp64", sizing="equal", K=0.0, nrhs_hint=0,
               nrhs_max=64, boost_tau=-1.0, max_refine=-1, refine_tol=1e-13,
               tree="balanced") -> Opts:
+    """spike_opts from keyword options (the header documents each field):
+    precision "fp64" | "mixed", sizing "equal" | "r13", tree "balanced" |
+    "paper" (the 2^m + r layout, which rejects other p)."""
     o = Opts()
     lib().spike_default_opts(ctypes.byref(o))
     o.p = int(p)
