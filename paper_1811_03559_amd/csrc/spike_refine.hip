@@ -1,9 +1,7 @@
 // FP64 residual, backward error and iterative-refinement driver.
 //
-// The residual R = F - op(A) X reads the caller's FP64 band directly.  For
-// op(A) = A a workgroup owns 256 consecutive rows and walks the band columns
-// that touch them, so each band column segment is read once with coalesced
-// accesses; for op(A) = A^T a wavefront owns an output row (a band column).
+// The residual R = F - op(A) X reads the caller's FP64 band directly; a
+// wavefront owns 64 consecutive output rows for both operations.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -130,9 +128,6 @@ __global__ __launch_bounds__(RT) void k_copy_cols(const double* S, int64_t lds, 
   }
 }
 
-// Right-hand sides handled per pass over the band (accumulators per thread)
-// by the transposed residual.
-constexpr int RQ = 16;
 
 // Lane `src` (wave-uniform) of v, for every lane: the value lands in scalar
 // registers, so the products that use it read no LDS.
@@ -143,19 +138,22 @@ __device__ __forceinline__ double lane_value(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
-// R = F - A X, plus per-column max |R| and max |X| (colred[2q], colred[2q+1]).
-// A wavefront owns 64 consecutive rows, a lane each; for every group of NQ
-// right-hand sides it walks the band columns touching its rows (coalesced
-// along each column) in rounds of 64, lane l holding row jb + l of the NQ
-// columns of X, which the products take lane by lane through scalar
-// registers.  RU band entries per lane are loaded before their products (an
-// entry outside the band reads the row's diagonal entry and enters as zero).
-// Each row's sum runs over the columns in ascending order.
-template <int NQ>
-__global__ __launch_bounds__(RT) void k_residual_n(const double* ab, int64_t ldab, int64_t n, int kl, int ku,
-                                                    const double* F, const double* X, int64_t ldx, double* R,
-                                                    int64_t ld, int nrhs, unsigned long long* colred,
-                                                    const int32_t* skip) {
+// R = F - op(A) X, plus per-column max |R| and max |X| (colred[2q],
+// colred[2q+1]).  A wavefront owns 64 consecutive output rows i, a lane each;
+// for every group of NQ right-hand sides it walks the j that couple to its
+// rows in rounds of 64, lane l holding row jb + l of the NQ columns of X,
+// which the products take lane by lane through scalar registers.  The entry
+// is A(i, j) for op(A) = A (band column j: the lanes' loads are coalesced)
+// and A(j, i) for A^T (band column i: each lane streams its own column,
+// which its cache lines then serve for the following j).  RU entries per
+// lane are loaded before their products (an entry outside the band reads
+// the row's diagonal entry and enters as zero).  Each row's sum runs over j
+// in ascending order.
+template <int NQ, bool TRANS>
+__global__ __launch_bounds__(RT) void k_residual(const double* ab, int64_t ldab, int64_t n, int kl, int ku,
+                                                  const double* F, const double* X, int64_t ldx, double* R,
+                                                  int64_t ld, int nrhs, unsigned long long* colred,
+                                                  const int32_t* skip) {
   if (*skip) return;
   __shared__ double red[2][RT / 64][NQ];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -164,9 +162,11 @@ __global__ __launch_bounds__(RT) void k_residual_n(const double* ab, int64_t lda
   const int64_t i = w0 + lane;
   const bool live = i < n;
   const int64_t home = live ? ku + i * ldab : 0;   // stand-in address: the row's diagonal entry
-  // band columns [jlo, jhi) hold all entries of this wavefront's rows
-  const int64_t jlo = w0 - kl > 0 ? w0 - kl : 0;
-  const int64_t jhi = w0 + 64 + ku < n ? w0 + 64 + ku : n;
+  // j couples to row i when i - j lies in [-lo_r, hi_r]: [-ku, kl] for A,
+  // [-kl, ku] for A^T; [jlo, jhi) covers the wavefront's rows
+  const int hi_r = TRANS ? ku : kl, lo_r = TRANS ? kl : ku;
+  const int64_t jlo = w0 - hi_r > 0 ? w0 - hi_r : 0;
+  const int64_t jhi = w0 + 64 + lo_r < n ? w0 + 64 + lo_r : n;
   for (int q0 = 0; q0 < nrhs; q0 += NQ) {
     const int nq = nrhs - q0 < NQ ? nrhs - q0 : NQ;
     double acc[NQ];
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(RT) void k_residual_n(const double* ab, int64_t lda
         for (int u = 0; u < RU; ++u) {
           const int64_t j = jb + jj0 + u;
           const int64_t d = i - j;
-          const bool in = live && jj0 + u < nj && d <= kl && -d <= ku;
-          a[u] = gld(ab + (in ? (ku + d) + j * ldab : home));
+          const bool in = live && jj0 + u < nj && d <= hi_r && -d <= lo_r;
+          a[u] = gld(ab + (in ? (TRANS ? (ku - d) + i * ldab : (ku + d) + j * ldab) : home));
           a[u] = in ? a[u] : 0.0;
         }
 #pragma unroll
@@ -238,47 +238,6 @@ __global__ __launch_bounds__(RT) void k_residual_n(const double* ab, int64_t lda
       atomic_max_nonneg(&colred[2 * (q0 + t) + which], m);
     }
     __syncthreads();   // red is rewritten by the next group
-  }
-}
-
-// R = F - A^T X: wavefront per output row i (band column i of A).  The
-// column is read once per group of RQ right-hand sides; lanes keep partial
-// sums that are reduced across the wavefront at the end.
-__global__ __launch_bounds__(RT) void k_residual_t(const double* ab, int64_t ldab, int64_t n, int kl, int ku,
-                                                    const double* F, const double* X, int64_t ldx, double* R,
-                                                    int64_t ld, int nrhs, unsigned long long* colred,
-                                                    const int32_t* skip) {
-  if (*skip) return;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t i = (int64_t)blockIdx.x * (RT / 64) + wave;
-  if (i >= n) return;
-  const int w = kl + ku + 1;
-  for (int q0 = 0; q0 < nrhs; q0 += RQ) {
-    const int nq = nrhs - q0 < RQ ? nrhs - q0 : RQ;
-    double acc[RQ];
-#pragma unroll
-    for (int t = 0; t < RQ; ++t) acc[t] = 0.0;
-    for (int s = lane; s < w; s += 64) {
-      const int64_t j = i + s - ku;   // A(j, i) at ab[s + i*ldab]
-      if (j < 0 || j >= n) continue;
-      const double a = ab[s + i * ldab];
-#pragma unroll
-      for (int t = 0; t < RQ; ++t)
-        if (t < nq) acc[t] = fma(a, X[j + (int64_t)(q0 + t) * ldx], acc[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < RQ; ++t) {
-      if (t >= nq) break;
-      double v = acc[t];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0) {
-        const int q = q0 + t;
-        double r = F[i + (int64_t)q * ld] - v;
-        R[i + (int64_t)q * ld] = r;
-        atomic_max_nonneg(&colred[2 * q], fabs(r));
-        atomic_max_nonneg(&colred[2 * q + 1], fabs(X[i + (int64_t)q * ldx]));
-      }
-    }
   }
 }
 
@@ -359,27 +318,18 @@ int refined_solve(const KParams& k, const LaunchCfg& c, const Plan& pl, char* ws
   if (int e = launch_solve(k, c, st, B, ldb, nrhs, trans)) return e;
   KParams kr = k;
   kr.skip = skip;
-  const unsigned rblocks_n = (unsigned)((n + RT - 1) / RT);
-  const unsigned rblocks_t = (unsigned)((n + RT / 64 - 1) / (RT / 64));
+  const unsigned rblocks = (unsigned)((n + RT - 1) / RT);
   for (int it = 0; it <= pl.max_refine; ++it) {
-    if (!trans) {
-      ProfScope ps("k_residual_n", st);
-      if (nrhs == 1)
-        hipLaunchKernelGGL(k_residual_n<1>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
-                           B, ldb, Rr, n, nrhs, colred, skip);
-      else if (nrhs <= 8)
-        hipLaunchKernelGGL(k_residual_n<8>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
-                           B, ldb, Rr, n, nrhs, colred, skip);
-      else if (nrhs <= 16)
-        hipLaunchKernelGGL(k_residual_n<16>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
-                           B, ldb, Rr, n, nrhs, colred, skip);
-      else
-        hipLaunchKernelGGL(k_residual_n<32>, dim3(rblocks_n), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc,
-                           B, ldb, Rr, n, nrhs, colred, skip);
-    } else {
-      ProfScope ps("k_residual_t", st);
-      hipLaunchKernelGGL(k_residual_t, dim3(rblocks_t), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc, B,
-                         ldb, Rr, n, nrhs, colred, skip);
+    {
+      ProfScope ps(trans ? "k_residual_t" : "k_residual_n", st);
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(rblocks), dim3(RT), 0, st, k.dAB, k.ldab, n, pl.kl, pl.ku, Fc, B, ldb, Rr,
+                           n, nrhs, colred, skip);
+      };
+      if (nrhs == 1) trans ? go(k_residual<1, true>) : go(k_residual<1, false>);
+      else if (nrhs <= 8) trans ? go(k_residual<8, true>) : go(k_residual<8, false>);
+      else if (nrhs <= 16) trans ? go(k_residual<16, true>) : go(k_residual<16, false>);
+      else trans ? go(k_residual<32, true>) : go(k_residual<32, false>);
     }
     if (int e = chk()) return e;
     hipLaunchKernelGGL(k_berr, dim3(1), dim3(64), 0, st, k.status, colred, nrhs, trans ? 1 : 0, pl.refine_tol, it,
