@@ -108,8 +108,11 @@ typedef struct spike_opts {
 typedef struct spike_status {
     int64_t info;       /* 0; i in [1, n]: first exactly-zero pivot at global
                            row i (1-based), boosting off or pivoting;
-                           n + 1 + j: interface system j (0-based, between
-                           partitions j and j+1) is singular               */
+                           n + j, j in [1, p-1]: the interface system of
+                           merge j is singular, merge j being the one
+                           between partitions j and j+1 (1-based), i.e.
+                           the first with an exactly-zero pivot in its
+                           partial-pivoting LU                           */
     int32_t n_boosts;   /* pivots boosted during the factorisation        */
     int32_t refine_iters; /* refinement iterations of the last solve      */
     double min_abs_pivot; /* smallest |u_jj| over all blocks              */
@@ -292,9 +295,9 @@ SPIKE_API int spike_graph_destroy(spike_graph g);
 /* Serving runtime (a project addition: many requests of mixed n, bandwidth
  * and nrhs on one GPU, reusing the paper's factor-once, solve-many structure
  * (factorisation reused by the transpose solve, section "Transpose solve
- * option") across requests).  The server owns one device allocation of
- * hbm_budget bytes made at creation (its only allocation), carves
- * factorisation workspaces out of it, keeps them resident per matrix id and
+ * option") across requests).  The caller hands the server a device pool of
+ * hbm_budget bytes (the library allocates no device memory); the server
+ * carves factorisation workspaces out of it, keeps them resident per matrix id and
  * evicts idle ones least-recently-used when a new matrix needs room.  A
  * worker thread admits queued requests while request slots and pool memory
  * are free (continuous batching: requests that arrive while others run are
@@ -314,6 +317,10 @@ typedef struct spike_server_opts {
     int32_t max_inflight; /* requests on the device at once              [64] */
     int32_t streams;      /* device streams work is spread over (1..16)   [4] */
     int32_t batch_window; /* solves fused into one batched launch        [32] */
+    void *dpool;          /* device pool of hbm_budget bytes, 256-byte
+                             aligned, allocated by the caller and kept
+                             alive until spike_server_destroy returns;
+                             required                                 [NULL] */
 } spike_server_opts;
 
 typedef struct spike_request {
@@ -348,7 +355,9 @@ typedef struct spike_server_report {
 } spike_server_report;
 
 SPIKE_API void spike_server_default_opts(spike_server_opts *opts);
-/* Errors: -1 bad options, -2 out NULL, -1000-hipError (allocation, streams). */
+/* Creates the server's streams and worker thread.  Errors: -1 bad options
+ * (including a NULL or misaligned dpool), -2 out NULL, -1000-hipError
+ * (stream creation). */
 SPIKE_API int spike_server_create(const spike_server_opts *opts, spike_server *out);
 /* Queue a request (non-blocking).  Errors: -1 bad server, -2 bad request,
  * -3 ticket NULL. */

@@ -114,7 +114,10 @@ __global__ void k_refine_begin(DevStatus* st, unsigned long long* colred, int nr
   if (threadIdx.x == 0) {
     st->refine_iters = 0;
     st->berr = -1.0;
-    st->skip = st->refine_active ? 0 : 1;
+    // a failed factorisation (zero pivot, singular interface) leaves every
+    // solve kernel idle; the refinement kernels idle with them, so B stays F
+    const bool failed = st->zero_row != ULLONG_MAX || st->iface != ULLONG_MAX;
+    st->skip = (st->refine_active && !failed) ? 0 : 1;
   }
   for (int q = threadIdx.x; q < 2 * nrhs; q += blockDim.x) colred[q] = 0ull;
 }

@@ -2,7 +2,8 @@
 //
 // Requests name a matrix by an id chosen by the caller.  The first request
 // for an id factors the matrix into a workspace carved from the server's
-// device pool (one allocation of the HBM budget made at creation); later
+// device pool (hbm_budget bytes of device memory the caller allocates and
+// passes in; the server allocates no device memory itself); later
 // requests for the id reuse the resident factorisation.  Resident
 // factorisations are evicted least-recently-used, when idle, to make room.
 // A worker thread admits pending requests while request slots and pool
@@ -16,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdint>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -347,6 +349,7 @@ void spike_server_default_opts(spike_server_opts* o) {
   o->max_inflight = 64;
   o->streams = 4;
   o->batch_window = 32;
+  o->dpool = nullptr;
 }
 
 int spike_server_create(const spike_server_opts* opts, spike_server* out) {
@@ -354,19 +357,15 @@ int spike_server_create(const spike_server_opts* opts, spike_server* out) {
   spike_server_opts o;
   spike_server_default_opts(&o);
   if (opts) o = *opts;
-  if (o.hbm_budget < 4096 || o.max_inflight < 1 || o.streams < 1 || o.streams > 16 || o.batch_window < 1)
+  if (o.hbm_budget < 4096 || o.max_inflight < 1 || o.streams < 1 || o.streams > 16 || o.batch_window < 1 ||
+      o.dpool == nullptr || (reinterpret_cast<uintptr_t>(o.dpool) & 255u) != 0)
     return -1;
   spike_server s = new (std::nothrow) spike_server_s();
   if (!s) return SPIKE_ERR_HIP - (int)hipErrorOutOfMemory;
   s->o = o;
   (void)hipGetDevice(&s->device);
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, o.hbm_budget);
-  if (e != hipSuccess) {
-    delete s;
-    return SPIKE_ERR_HIP - (int)e;
-  }
-  s->base = static_cast<char*>(p);
+  s->base = static_cast<char*>(o.dpool);
+  hipError_t e = hipSuccess;
   s->pool = new Pool(o.hbm_budget);
   for (int i = 0; i < o.streams; ++i) {
     hipStream_t st = nullptr;
@@ -376,7 +375,6 @@ int spike_server_create(const spike_server_opts* opts, spike_server* out) {
   }
   if ((int)s->streams.size() != o.streams) {
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-    (void)hipFree(p);
     delete s->pool;
     delete s;
     return SPIKE_ERR_HIP - (int)e;
@@ -507,7 +505,6 @@ int spike_server_destroy(spike_server s) {
   }
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-  (void)hipFree(s->base);
   delete s->pool;
   s->magic = 0;
   delete s;

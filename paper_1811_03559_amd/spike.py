@@ -56,7 +56,7 @@ class TuneResult(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", _c_size), ("max_inflight", _c_i32), ("streams", _c_i32),
-                ("batch_window", _c_i32)]
+                ("batch_window", _c_i32), ("dpool", _c_p)]
 
 
 class Request(ctypes.Structure):
@@ -245,6 +245,31 @@ def workspace_size(n, kl, ku, **opts) -> int:
     return out.value
 
 
+def _check_band(ab, kl, ku):
+    """A band handed to the library: a contiguous float64 CUDA tensor of shape
+    (n, ldab) with ldab >= kl + ku + 1 (checked before any library call)."""
+    import torch
+    if not isinstance(ab, torch.Tensor) or ab.dtype != torch.float64 or not ab.is_cuda \
+            or ab.dim() != 2 or not ab.is_contiguous():
+        raise ValueError("band must be a contiguous 2-D float64 CUDA tensor (n, ldab)")
+    if int(ab.shape[1]) < int(kl) + int(ku) + 1:
+        raise ValueError("band has ldab = %d < kl + ku + 1" % int(ab.shape[1]))
+
+
+def _check_rhs(B, n):
+    """A right-hand side handed to the library: a float64 CUDA tensor of shape
+    (nrhs, n) or (n,) with unit column stride.  Returns the 2-D view."""
+    import torch
+    if not isinstance(B, torch.Tensor) or B.dtype != torch.float64 or not B.is_cuda:
+        raise ValueError("B must be a float64 CUDA tensor")
+    if B.dim() == 1:
+        B = B.view(1, -1)
+    if B.dim() != 2 or B.shape[1] != n or (B.shape[1] > 1 and B.stride(1) != 1) \
+            or (B.shape[0] > 1 and B.stride(0) < max(n, 1)):
+        raise ValueError("B must have shape (nrhs, n) with unit column stride")
+    return B
+
+
 def _stream_handle(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -259,8 +284,7 @@ class Factorization:
 
     def __init__(self, ab, kl, ku, *, stream=None, workspace=None, **opts):
         import torch
-        if ab.dtype != torch.float64 or not ab.is_cuda or not ab.is_contiguous():
-            raise ValueError("band must be a contiguous float64 CUDA tensor")
+        _check_band(ab, kl, ku)
         self.n, self.ldab = int(ab.shape[0]), int(ab.shape[1])
         self.kl, self.ku = int(kl), int(ku)
         self.opts = make_opts(**opts)
@@ -283,13 +307,7 @@ class Factorization:
 
     def solve_(self, B, *, trans=False, stream=None):
         """In-place solve on B ((nrhs, n) float64 CUDA tensor, C order)."""
-        import torch
-        if B.dtype != torch.float64 or not B.is_cuda:
-            raise ValueError("B must be a float64 CUDA tensor")
-        if B.dim() == 1:
-            B = B.view(1, -1)
-        if B.shape[1] != self.n or B.stride(1) != 1:
-            raise ValueError("B must have shape (nrhs, n) with unit column stride")
+        B = _check_rhs(B, self.n)
         ldb = B.stride(0) if B.shape[0] > 1 else max(self.n, 1)
         fn = lib().spike_solve_transpose if trans else lib().spike_solve
         rc = fn(self.h, int(B.shape[0]), ctypes.c_void_p(B.data_ptr()), int(ldb), _stream_handle(stream))
@@ -336,16 +354,15 @@ def _batch_arrays(facs, Bs, trans):
         raise ValueError("one right-hand side per factorisation")
     if isinstance(trans, bool):
         trans = [trans] * cnt
+    for f, B in zip(facs, Bs):
+        _check_rhs(B, f.n)
     hs = (_c_p * cnt)(*[f.h.value for f in facs])
     nr = (_c_i32 * cnt)()
     bp = (_c_p * cnt)()
     ld = (_c_i64 * cnt)()
     tr = (_c_i32 * cnt)(*[1 if t else 0 for t in trans])
     for i, (f, B) in enumerate(zip(facs, Bs)):
-        if B.dim() == 1:
-            B = B.view(1, -1)
-        if B.shape[1] != f.n or B.stride(1) != 1:
-            raise ValueError("B must have shape (nrhs, n) with unit column stride")
+        B = _check_rhs(B, f.n)
         nr[i] = int(B.shape[0])
         bp[i] = B.data_ptr()
         ld[i] = B.stride(0) if B.shape[0] > 1 else max(f.n, 1)
@@ -402,6 +419,7 @@ def autotune(ab, kl, ku, nrhs=1, stream=None, **base):
     """Pick p and the partition sizing for this matrix and nrhs by timing
     candidate plans (spike_autotune).  Returns (opts dict, result dict)."""
     import torch
+    _check_band(ab, kl, ku)
     n, ldab = int(ab.shape[0]), int(ab.shape[1])
     o = make_opts(**base)
     need = _c_size()
@@ -429,11 +447,17 @@ class Server:
     factorisations, HBM-budgeted admission and continuous batching.  Tensors
     handed to submit() are kept referenced until release()."""
 
-    def __init__(self, hbm_budget=16 << 30, max_inflight=64, streams=4, batch_window=32):
+    def __init__(self, hbm_budget=16 << 30, max_inflight=64, streams=4, batch_window=32, device=None):
+        import torch
         o = ServerOpts()
         lib().spike_server_default_opts(ctypes.byref(o))
         o.hbm_budget, o.max_inflight, o.streams, o.batch_window = int(hbm_budget), int(max_inflight), \
             int(streams), int(batch_window)
+        # the device pool the server carves workspaces from (the library
+        # allocates no device memory); kept referenced until close()
+        self._pool = torch.empty(max(int(hbm_budget), 4096), dtype=torch.uint8,
+                                 device=device if device is not None else torch.device("cuda"))
+        o.dpool = self._pool.data_ptr()
         s = _c_p()
         rc = lib().spike_server_create(ctypes.byref(o), ctypes.byref(s))
         if rc != 0:
@@ -444,11 +468,9 @@ class Server:
     def submit(self, matrix_id, ab, kl, ku, B, trans=False, **opts):
         """Queue op(A) X = B for matrix ``matrix_id`` (band tensor ``ab``,
         (n, ldab)); B: (nrhs, n) float64 CUDA tensor, solved in place."""
-        if B.dim() == 1:
-            B = B.view(1, -1)
+        _check_band(ab, kl, ku)
         n = int(ab.shape[0])
-        if B.shape[1] != n or B.stride(1) != 1:
-            raise ValueError("B must have shape (nrhs, n) with unit column stride")
+        B = _check_rhs(B, n)
         r = Request()
         r.matrix_id, r.n, r.kl, r.ku = int(matrix_id), n, int(kl), int(ku)
         r.dAB, r.ldab = ab.data_ptr(), int(ab.shape[1])
@@ -504,6 +526,7 @@ class Server:
             lib().spike_server_destroy(self.s)
             self.s = None
             self._keep.clear()
+            self._pool = None
 
     def __del__(self):
         try:

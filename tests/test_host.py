@@ -196,6 +196,12 @@ def test_server_argument_errors_need_no_device():
     bad = spike.ServerOpts(hbm_budget=1 << 20, max_inflight=4, streams=17, batch_window=1)
     assert L.spike_server_create(ctypes.byref(bad), ctypes.byref(s)) == -1
     assert L.spike_server_create(None, None) == -2
+    # the caller provides the device pool: a missing or misaligned one is refused
+    # before anything touches a device
+    assert o.dpool is None
+    assert L.spike_server_create(ctypes.byref(o), ctypes.byref(s)) == -1
+    odd = spike.ServerOpts(hbm_budget=1 << 20, max_inflight=4, streams=1, batch_window=1, dpool=0x1008)
+    assert L.spike_server_create(ctypes.byref(odd), ctypes.byref(s)) == -1
     st = spike.RequestStatus()
     rep = spike.ServerReport()
     t = ctypes.c_int64()
@@ -206,3 +212,44 @@ def test_server_argument_errors_need_no_device():
     assert L.spike_server_drain(None) == -1
     assert L.spike_server_stats(None, ctypes.byref(rep)) == -1
     assert L.spike_server_destroy(None) == -1
+
+
+def test_binding_rejects_bad_tensors_before_any_library_call(monkeypatch):
+    """Every binding entry point that hands tensor pointers to the library
+    refuses float32, host-resident and transposed (non-contiguous) tensors with
+    ValueError before it calls into the library."""
+    import types
+    import torch
+
+    calls = []
+
+    class Trap:
+        def __getattr__(self, name):
+            calls.append(name)
+            raise AssertionError("library called: " + name)
+
+    monkeypatch.setattr(spike, "lib", lambda: Trap())
+    n, kl, ku = 40, 2, 3
+    good_ab = torch.zeros((n, kl + ku + 1), dtype=torch.float64)
+    bad_bands = [good_ab.float(), good_ab,                       # float32; host (no CUDA here)
+                 torch.zeros((kl + ku + 1, n), dtype=torch.float64).t()]   # transposed view
+    for ab in bad_bands:
+        with pytest.raises(ValueError):
+            spike.Factorization(ab, kl, ku)
+        with pytest.raises(ValueError):
+            spike.autotune(ab, kl, ku)
+        srv = spike.Server.__new__(spike.Server)
+        with pytest.raises(ValueError):
+            srv.submit(1, ab, kl, ku, torch.zeros((1, n), dtype=torch.float64))
+    # right-hand sides: a fake factorisation that fails if its handle is read
+    fac = types.SimpleNamespace(n=n)
+    bad_rhs = [torch.zeros((2, n), dtype=torch.float32), torch.zeros((2, n), dtype=torch.float64),
+               torch.zeros((n, 2), dtype=torch.float64).t(), torch.zeros((2, n + 1), dtype=torch.float64)]
+    for B in bad_rhs:
+        with pytest.raises(ValueError):
+            spike.solve_batch([fac], [B])
+        with pytest.raises(ValueError):
+            spike.Factorization.solve_(fac, B)
+        with pytest.raises(ValueError):
+            spike._check_rhs(B, n)
+    assert calls == []

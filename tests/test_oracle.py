@@ -294,3 +294,69 @@ def test_r13_reproduces_paper_table():
         r = oracle.r13(4.0 / 3.0, float(nrhs) / 160.0)
         assert abs(r - float(r13_paper)) <= 0.11
         assert abs(r / 2 - float(r12_paper)) <= 0.06
+
+
+# ---------------------------------------------------------------- one factorisation, two solves
+
+@pytest.mark.parametrize("kl,ku", [(0, 0), (2, 5), (5, 2), (4, 4)])
+@pytest.mark.parametrize("pivot", [False, True])
+def test_gbsv_nt_matches_separate_solves_and_dense(kl, ku, pivot):
+    """orc_gbsv_nt (the CPU-baseline routine: one factorisation, then the A and
+    A^T solves) returns bitwise what two separate orc_gbsv calls return, and
+    both solutions agree with dense LAPACK solves of A and A^T."""
+    n = 53
+    ab = rand_band(n, kl, ku, 400 + 10 * kl + ku, dominant=not pivot)
+    A = dense_from_band(ab, kl, ku)
+    F = inputs.rhs(n, 3, inputs.rng_for(17))
+    X, Xt = oracle.gbsv_nt(ab, kl, ku, F, pivot=pivot)
+    np.testing.assert_array_equal(X, oracle.gbsv(ab, kl, ku, F, pivot=pivot))
+    np.testing.assert_array_equal(Xt, oracle.gbsv(ab, kl, ku, F, pivot=pivot, trans=True))
+    kappa = np.linalg.cond(A, 1)
+    assert oracle.fwd_err(X, np.linalg.solve(A, F.T).T) <= 1e-14 * kappa * n
+    assert oracle.fwd_err(Xt, np.linalg.solve(A.T, F.T).T) <= 1e-14 * kappa * n
+    # off the diagonal A is not symmetric, so the two solutions differ: a
+    # routine that returned the same solve for both would fail here
+    if kl + ku > 0:
+        assert oracle.fwd_err(X, Xt) > 1e-6
+
+
+def test_gbsv_nt_degenerate():
+    """n = 0 is a no-op; a zero pivot is reported and leaves both right-hand
+    sides untouched."""
+    X, Xt = oracle.gbsv_nt(np.zeros((0, 3)), 1, 1, np.zeros((2, 0)))
+    assert X.shape == (2, 0) and Xt.shape == (2, 0)
+    ab = band_from_dense(np.diag([1.0, 0.0, 2.0]), 1, 1)
+    with pytest.raises(ZeroDivisionError):
+        oracle.gbsv_nt(ab, 1, 1, np.ones((1, 3)), pivot=False)
+
+
+# ---------------------------------------------------------------- transpose via explicit A^T
+
+def transpose_band(ab, kl, ku):
+    """Band storage of A^T (kl and ku swapped), built entry by entry."""
+    n = ab.shape[0]
+    at = np.zeros((n, kl + ku + 1))
+    for j in range(n):
+        for i in range(max(0, j - ku), min(n, j + kl + 1)):
+            # A(i, j) becomes A^T(j, i), stored in column i with ku' = kl
+            at[i, kl + j - i] = ab[j, ku + i - j]
+    return at
+
+
+@pytest.mark.parametrize("kl,ku", [(1, 1), (2, 5), (5, 2), (0, 3), (3, 0), (6, 6)])
+@pytest.mark.parametrize("pivot", [False, True])
+def test_transpose_solve_against_explicit_transpose(kl, ku, pivot):
+    """The transpose solve (U^T then L^T with the interchanges undone) equals
+    a fresh factorisation of A^T, stored as a band with kl and ku swapped,
+    followed by the plain non-transpose solve."""
+    n = 211
+    ab = rand_band(n, kl, ku, 900 + 10 * kl + ku, dominant=not pivot)
+    at = transpose_band(ab, kl, ku)
+    np.testing.assert_array_equal(dense_from_band(at, ku, kl), dense_from_band(ab, kl, ku).T)
+    F = inputs.rhs(n, 2, inputs.rng_for(23))
+    Xt = oracle.gbsv(ab, kl, ku, F, pivot=pivot, trans=True)
+    Xe = oracle.gbsv(at, ku, kl, F, pivot=pivot)
+    kappa = oracle.cond1(ab, kl, ku)
+    assert oracle.fwd_err(Xt, Xe) <= 1e-14 * kappa * n
+    assert oracle.relres(ab, kl, ku, Xt, F, trans=True) <= 1e-14
+    assert oracle.relres(at, ku, kl, Xe, F) <= 1e-14
