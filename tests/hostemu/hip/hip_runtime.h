@@ -5,6 +5,7 @@
 // slot array, and every dynamic LDS buffer is its own heap allocation of the
 // launch's size, so AddressSanitizer reports any access outside it.
 #pragma once
+#include <atomic>
 #include <cmath>
 #include <condition_variable>
 #include <cstdint>
@@ -41,22 +42,27 @@ extern EmuIdx blockDim, gridDim;
 
 namespace emu {
 
+// Barrier over the threads of a workgroup (or wavefront) that have not
+// returned: arrivals spin (yielding) on a generation counter; a thread that
+// returns leaves, and releases the others when it was the last one missing.
 struct Barrier {
   std::mutex mu;
-  std::condition_variable cv;
+  std::atomic<unsigned long> gen{0};
   int active = 0, arrived = 0;
-  unsigned long gen = 0;
   void reset(int n) { active = n; arrived = 0; }
   void arrive() {
-    std::unique_lock<std::mutex> lk(mu);
-    const unsigned long g = gen;
-    if (++arrived >= active) { arrived = 0; ++gen; cv.notify_all(); return; }
-    cv.wait(lk, [&] { return gen != g; });
+    unsigned long g;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      g = gen.load();
+      if (++arrived >= active) { arrived = 0; gen.fetch_add(1); return; }
+    }
+    while (gen.load(std::memory_order_acquire) == g) std::this_thread::yield();
   }
   void leave() {
     std::lock_guard<std::mutex> lk(mu);
     --active;
-    if (arrived > 0 && arrived >= active) { arrived = 0; ++gen; cv.notify_all(); }
+    if (arrived > 0 && arrived >= active) { arrived = 0; gen.fetch_add(1); }
   }
 };
 

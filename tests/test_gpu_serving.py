@@ -9,15 +9,28 @@ from paper_1811_03559_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-POOL = [(2000, 4, 2), (3000, 8, 3), (5000, 16, 5), (2600, 8, 1), (4000, 32, 4), (3300, 16, 7)]
+# (n, k, p, class): FP64 dominant (cfg1 recipe), FP32 factors with FP64
+# refinement (cfg3 recipe), pivoting-class (cfg2 recipe: N(0,1) band, rows
+# scaled by 10^U[-4,4]) factored with partial pivoting, unrefined at p = 2
+# and with FP64 refinement at p = 3
+POOL = [(2000, 4, 2, "fp64"), (3000, 8, 3, "fp64"), (5000, 16, 5, "fp64"), (2600, 8, 1, "fp64"),
+        (4000, 32, 4, "mixed"), (3300, 16, 7, "mixed"), (2500, 8, 2, "pivot"), (3000, 4, 3, "pivot_refined")]
+OPTS = {"fp64": {}, "mixed": {"precision": "mixed"}, "pivot": {"pivot": True},
+        "pivot_refined": {"pivot": True, "max_refine": 3}}
 
 
 def _pool():
     import torch
     mats = []
-    for i, (n, k, p) in enumerate(POOL):
-        ab = inputs.band_dominant(n, k, k, inputs.rng_for(6100 + i), diag_mult=1.05, diag_add=0.0)
-        mats.append((ab, torch.from_numpy(ab).cuda(), k, p))
+    for i, (n, k, p, cls) in enumerate(POOL):
+        rng = inputs.rng_for(6100 + i)
+        if cls == "fp64":
+            ab = inputs.band_dominant(n, k, k, rng, diag_mult=1.05, diag_add=0.0)
+        elif cls == "mixed":
+            ab = inputs.band_dominant(n, k, k, rng, diag_mult_range=(1.01, 1.5))
+        else:
+            ab = inputs.band_gaussian_rowscaled(n, k, k, rng)
+        mats.append((ab, torch.from_numpy(ab).cuda(), k, p, OPTS[cls]))
     return mats
 
 
@@ -28,21 +41,27 @@ def _requests(nreq, seed):
 
 
 def test_results_same_alone_and_in_the_mix():
+    """64 requests over FP64, FP32-with-refinement and pivoting-class
+    matrices (refined and not), 30 % transpose solves, through a server
+    whose pool holds about three factorisations (evictions happen): every
+    result is bitwise the same request factored and solved alone, and
+    sampled results meet the oracle's bars."""
     import torch
     from paper_1811_03559_amd import spike
     mats = _pool()
-    reqs = _requests(60, 6200)
+    reqs = _requests(64, 6200)
+    assert {POOL[m][3] for m, _, _ in reqs} == set(OPTS)
     Fs = [inputs.rhs(POOL[m][0], nr, inputs.rng_for(6300 + i)) for i, (m, nr, _) in enumerate(reqs)]
     # budget for about three resident factorisations: forces evictions
-    budget = 3 * max(spike.workspace_size(n, k, k, p=p) for n, k, p in POOL)
+    budget = 3 * max(spike.workspace_size(n, k, k, p=p, **OPTS[c]) for n, k, p, c in POOL)
     srv = spike.Server(hbm_budget=budget, max_inflight=16, streams=3, batch_window=8)
     Bs, tickets = [], []
     for i, (m, nr, tr) in enumerate(reqs):
-        ab, dab, k, p = mats[m]
+        ab, dab, k, p, opts = mats[m]
         B = torch.from_numpy(Fs[i].copy()).cuda()
         Bs.append(B)
         torch.cuda.synchronize()
-        tickets.append(srv.submit(m, dab, k, k, B, trans=tr, p=p))
+        tickets.append(srv.submit(m, dab, k, k, B, trans=tr, p=p, **opts))
     sts = [srv.wait(t) for t in tickets]
     torch.cuda.synchronize()
     for st in sts:
@@ -54,16 +73,18 @@ def test_results_same_alone_and_in_the_mix():
     for t in tickets:
         srv.release(t)
     srv.close()
+    checked = set()
     for i, (m, nr, tr) in enumerate(reqs):
-        ab, dab, k, p = mats[m]
-        fac = spike.Factorization(dab, k, k, p=p)
+        ab, dab, k, p, opts = mats[m]
+        fac = spike.Factorization(dab, k, k, p=p, **opts)
         B = torch.from_numpy(Fs[i].copy()).cuda()
         fac.solve_(B, trans=tr)
         torch.cuda.synchronize()
         X = B.cpu().numpy()
-        assert np.array_equal(X, Bs[i].cpu().numpy()), i
-        if i % 10 == 0:
-            check(ab, k, k, Fs[i], X, trans=tr, pivot=False)
+        assert np.array_equal(X, Bs[i].cpu().numpy()), (i, POOL[m])
+        if (m, tr) not in checked:
+            checked.add((m, tr))
+            check(ab, k, k, Fs[i], X, trans=tr, pivot=bool(opts.get("pivot")))
         fac.close()
 
 

@@ -253,3 +253,39 @@ def test_binding_rejects_bad_tensors_before_any_library_call(monkeypatch):
         with pytest.raises(ValueError):
             spike._check_rhs(B, n)
     assert calls == []
+
+
+def test_factor_argument_errors_need_no_device():
+    """spike_factor validates its arguments on the host, in argument order,
+    before it touches the device: -5 for ldab < kl + ku + 1, -7 for a NULL or
+    misaligned workspace, -8 for a workspace smaller than the planner's size,
+    -10 for a NULL handle pointer (the device pointers below are never
+    dereferenced)."""
+    import ctypes
+    L = spike.lib()
+    n, kl, ku = 1000, 3, 2
+    o = spike.make_opts(p=4)
+    need = spike.workspace_size(n, kl, ku, p=4)
+    fake_ab = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)             # 256-byte aligned
+    h = ctypes.c_void_p()
+    f = L.spike_factor
+    assert f(-1, kl, ku, fake_ab, 6, ctypes.byref(o), ws, need, None, ctypes.byref(h)) == -1
+    assert f(n, -1, ku, fake_ab, 6, ctypes.byref(o), ws, need, None, ctypes.byref(h)) == -2
+    assert f(n, kl, -1, fake_ab, 6, ctypes.byref(o), ws, need, None, ctypes.byref(h)) == -3
+    assert f(n, kl, ku, None, 6, ctypes.byref(o), ws, need, None, ctypes.byref(h)) == -4
+    assert f(n, kl, ku, fake_ab, kl + ku, ctypes.byref(o), ws, need, None, ctypes.byref(h)) == -5
+    bad = spike.make_opts(p=n + 1)
+    assert f(n, kl, ku, fake_ab, 6, ctypes.byref(bad), ws, need, None, ctypes.byref(h)) == -6
+    assert f(n, kl, ku, fake_ab, 6, ctypes.byref(o), None, need, None, ctypes.byref(h)) == -7
+    assert f(n, kl, ku, fake_ab, 6, ctypes.byref(o), ctypes.c_void_p(0x200008), need, None,
+             ctypes.byref(h)) == -7
+    assert f(n, kl, ku, fake_ab, 6, ctypes.byref(o), ws, need - 1, None, ctypes.byref(h)) == -8
+    assert f(n, kl, ku, fake_ab, 6, ctypes.byref(o), ws, need, None, None) == -10
+    assert h.value is None
+    # solves and queries on an invalid handle
+    assert L.spike_solve(None, 1, fake_ab, n, None) == -1
+    assert L.spike_solve_transpose(None, 1, fake_ab, n, None) == -1
+    st = spike.Status()
+    assert L.spike_info(None, ctypes.byref(st)) == -1
+    assert L.spike_destroy(None) == -1

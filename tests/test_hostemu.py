@@ -1,0 +1,79 @@
+"""CPU replay of the workgroup kernel path under AddressSanitizer.
+
+The partial-pivoting leaf kernels (factor with tips, D stage, retrieval, Z
+sweeps, transposed D stage), the generic interface-merge kernels and the
+transpose G-tip kernel are compiled for the host (tests/hostemu) and run with
+every workgroup as 256 host threads.  Every workspace region and every
+dynamic LDS buffer is its own allocation of the size the planner reserves,
+so an index outside its region stops the run.  The results must match the
+oracle to the GPU parity bars.
+
+The first cases are the exact inputs of the pivoting two-partition wide-band
+GPU parity cases (kl = ku = 200 and 160, NB = 16 panels, dense L panel tiles,
+the reversed-frame last partition)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_03559_amd import inputs
+
+sys.path.insert(0, os.path.join(os.path.dirname(__file__), "hostemu"))
+import replay  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    return replay.build(str(tmp_path_factory.mktemp("hostemu")))
+
+
+def _wide_band_case(k, p, nrhs=5):
+    # the inputs of test_gpu_parity.test_wide_band(k, p)
+    n = p * (2 * k + 37) + 3
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(9000 + k + p), diag_mult=1.05, diag_add=0.0)
+    F = inputs.rhs(n, nrhs, inputs.rng_for(k * p))
+    return ab, k, k, F
+
+
+def _check(ab, kl, ku, F, X, trans):
+    Xo = oracle.gbsv(ab, kl, ku, F, pivot=True, trans=trans)
+    kappa = oracle.cond1(ab, kl, ku)
+    assert oracle.relres(ab, kl, ku, X, F, trans=trans) <= 1e-13
+    assert oracle.fwd_err(X, Xo) <= 1e-11 * max(kappa, 1.0)
+
+
+@pytest.mark.parametrize("k", [200, 160])
+@pytest.mark.parametrize("trans", [False, True])
+def test_pivoting_two_partition_wide_band(exe, k, trans):
+    ab, kl, ku, F = _wide_band_case(k, 2)
+    info, X = replay.run(exe, ab, kl, ku, F, p=2, pivot=True, trans=trans)
+    assert info == 0
+    _check(ab, kl, ku, F, X, trans)
+
+
+@pytest.mark.parametrize("n,kl,ku,p,mult", [(600, 8, 8, 3, 0.3), (900, 5, 2, 5, 0.5), (700, 40, 17, 2, 0.2)])
+@pytest.mark.parametrize("trans", [False, True])
+def test_pivoting_with_row_swaps(exe, n, kl, ku, p, mult, trans):
+    """Not diagonally dominant: rows are exchanged inside every panel, and the
+    L panel tiles hold multipliers below the band."""
+    ab = inputs.band_dominant(n, kl, ku, inputs.rng_for(n + kl), diag_mult=mult)
+    _, _, ipiv = oracle.gbtrf(ab, kl, ku, pivot=True)
+    assert np.count_nonzero(ipiv != np.arange(n)) > 0
+    F = inputs.rhs(n, 3, inputs.rng_for(n))
+    info, X = replay.run(exe, ab, kl, ku, F, p=p, pivot=True, trans=trans)
+    assert info == 0
+    _check(ab, kl, ku, F, X, trans)
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_non_pivoting_generic_path(exe, trans):
+    """The non-pivoting workgroup kernels (the path of bandwidths beyond the
+    MFMA engines), with unequal bands and several partitions."""
+    n, kl, ku, p = 1500, 12, 5, 6
+    ab = inputs.band_dominant(n, kl, ku, inputs.rng_for(77))
+    F = inputs.rhs(n, 2, inputs.rng_for(78))
+    info, X = replay.run(exe, ab, kl, ku, F, p=p, pivot=False, trans=trans)
+    assert info == 0
+    _check(ab, kl, ku, F, X, trans)

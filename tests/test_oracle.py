@@ -360,3 +360,19 @@ def test_transpose_solve_against_explicit_transpose(kl, ku, pivot):
     assert oracle.fwd_err(Xt, Xe) <= 1e-14 * kappa * n
     assert oracle.relres(ab, kl, ku, Xt, F, trans=True) <= 1e-14
     assert oracle.relres(at, ku, kl, Xe, F) <= 1e-14
+
+
+def test_singular_coupling_makes_elimination_meet_a_zero_pivot():
+    """Two identity blocks coupled by A(m-1, m) = A(m, m-1) = 1 (rows m-1 and
+    m equal): the leaves are nonsingular but A is not, and partial-pivoting
+    elimination meets an exactly zero pivot (the matrix the GPU contract test
+    uses for a singular interface system)."""
+    for copies in (1, 8):
+        n = 4 * copies
+        m = n // 2
+        A = np.eye(n)
+        A[m - 1, m] = A[m, m - 1] = 1.0
+        ab = band_from_dense(A, 1, 1)
+        for pivot in (False, True):
+            with pytest.raises(ZeroDivisionError):
+                oracle.gbsv(ab, 1, 1, np.ones((1, n)), pivot=pivot)
