@@ -210,6 +210,26 @@ typedef struct spike_kernel_time {
 SPIKE_API int spike_profile_enable(int on);
 SPIKE_API int spike_profile_report(spike_kernel_time *out, int cap, int *count);
 
+/* Instrumented sweep counts, the measurement behind Table tab:sweeps of
+ * section "Optimizing per-partition costs" (full triangular sweeps per
+ * partition in the factorisation and solve stages; the transpose section
+ * states the transpose solve keeps the same counts).
+ * spike_sweep_counting(on): while on is nonzero, every later spike_factor
+ * sets up its handle to count, on the device, each triangular sweep of one
+ * column set (a spike block or the right-hand sides) over one partition's
+ * factors, in every kernel path (single and multiple right-hand sides,
+ * pivoting or not, batched or not).  Off by default; handles keep the
+ * setting they were made with.  Returns 0.
+ * spike_sweep_counts(h, out) (blocking copy; synchronise first) writes 24
+ * counters, out[(stage * 4 + type) * 2 + full]: stage 0 = factorisation,
+ * 1 = spike_solve, 2 = spike_solve_transpose (summed over all calls on h);
+ * type 0 = single partition (p = 1), 1 = first, 2 = middle, 3 = last; full
+ * 1 = the sweep ran over all rows of the partition, 0 = a truncated sweep
+ * over its trailing rows.  Errors: -1 bad handle, -2 out NULL, -3 h was not
+ * made while counting was on. */
+SPIKE_API int spike_sweep_counting(int on);
+SPIKE_API int spike_sweep_counts(spike_handle h, uint64_t *out);
+
 /* Release the host handle.  The caller may free dWork afterwards (after the
  * stream work using it has completed). */
 SPIKE_API int spike_destroy(spike_handle h);

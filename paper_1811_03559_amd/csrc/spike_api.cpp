@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <vector>
 #include <new>
@@ -15,6 +16,9 @@
 namespace {
 
 constexpr uint32_t kMagic = 0x5e1ce5u;
+
+// Handles made while this is set count their sweeps (spike_sweep_counting).
+std::atomic<int> g_count_sweeps{0};
 
 int check_hip(hipError_t e) { return e == hipSuccess ? 0 : SPIKE_ERR_HIP - (int)e; }
 
@@ -97,6 +101,7 @@ void fill_params(spike_handle h, const double* dAB, int64_t ldab) {
   k.sdinv = at<double>(w, pl.off_sdinv);
   k.sperm = at<int>(w, pl.off_sperm);
   k.mtmp = at<double>(w, pl.off_mtmp);
+  k.sweeps = g_count_sweeps.load() ? at<unsigned long long>(w, pl.off_sweeps) : nullptr;
 
   spike::LaunchCfg& c = h->cfg;
   c.nb = pl.nb;
@@ -404,6 +409,7 @@ int spike_factor(int64_t n, int32_t kl, int32_t ku, const double* dAB, int64_t l
   fill_params(h, dAB, ldab);
   int e = upload(h, stream);
   if (!e) e = spike::launch_init_status(h->kp.status, stream);
+  if (!e && h->kp.sweeps) e = spike::run_zero_counters(h->kp.sweeps, spike::kSweepCounters, stream);
   if (!e && n > 0) e = spike::launch_factor(h->kp, h->cfg, stream);
   if (!e && n > 0 && h->plan.refine_enabled()) e = spike::prepare_refine(h->kp, h->plan, h->ws, stream);
   if (e) {
@@ -441,6 +447,18 @@ int spike_info(spike_handle h, spike_status* out) {
   out->min_abs_pivot = mp;
   out->berr = s.berr;
   return 0;
+}
+
+int spike_sweep_counting(int on) {
+  g_count_sweeps.store(on ? 1 : 0);
+  return 0;
+}
+
+int spike_sweep_counts(spike_handle h, uint64_t* out) {
+  if (!valid(h)) return -1;
+  if (!out) return -2;
+  if (!h->kp.sweeps) return -3;
+  return check_hip(hipMemcpy(out, h->kp.sweeps, sizeof(uint64_t) * spike::kSweepCounters, hipMemcpyDeviceToHost));
 }
 
 int spike_handle_plan(spike_handle h, spike_plan_info* out) {

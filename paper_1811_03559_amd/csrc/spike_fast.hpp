@@ -115,6 +115,7 @@ __global__ __launch_bounds__(NT) void k_ftip_v(KParams k, int ncg) {
   }
   tile_sweep<T, HT, OP_L_FWD>(As, dv + (int64_t)(jv / 16) * dinv_stride(), src,
                               tdst(fs + jv, nullptr, is_f64<T>(), 1, m, m - jv, m - jv, m - jv), 64 * cg, kuf, lds);
+  if (cg == 0) note_sweep(k, 0, L.type, As.m, m);
   if (L.type == LEAF_MIDDLE) return;
   __syncthreads();
   // 2. side block: the bottom h rows of L^{-1}[0; B'], columns of this group
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(NT) void k_ftip_v(KParams k, int ncg) {
   TDst du = rev ? tdst(nullptr, tips.Wt(k.p - 1) + (ku - 1), 1, -1, kw, 0, bot, mu)
                 : tdst(nullptr, tips.Vb(0), 1, 1, kw, 0, bot, mu);
   tile_sweep<T, HT, OP_U_BWD>(Au, dv + (int64_t)(ju / 16) * dinv_stride(), su, du, 64 * cg, kuf, lds);
+  if (cg == 0) note_sweep(k, 0, L.type, Au.m, m);
 }
 
 template <typename T, int HT>
@@ -151,6 +153,7 @@ __global__ __launch_bounds__(NT) void k_ftip_w(KParams k, int ncg) {
   TSrc src = tsrc(ch, 1, 1, kl, 0, kl);
   TDst dst = tdst(fs + (int64_t)ku * m, nullptr, is_f64<T>(), 1, m, m, m, m);
   tile_sweep<T, HT, OP_L_FWD>(A, dv, src, dst, 64 * cg, kl, lds);
+  if (cg == 0) note_sweep(k, 0, L.type, A.m, m);   // W: L sweep
 }
 
 template <typename T, int HT>
@@ -169,6 +172,7 @@ __global__ __launch_bounds__(NT) void k_ftip_u(KParams k, int ncg) {
   double* tp = k.tips + (int64_t)li * kw * kw;
   TDst dst = tdst(tp, tp + ku, 1, 1, kw, ku, m - kl, m);
   tile_sweep<T, HT, OP_U_BWD>(A, dv, src, dst, 64 * cg, kw, lds);
+  if (cg == 0) note_sweep(k, 0, L.type, A.m, m, 2);   // V and W: one U pass
 }
 
 // ---------------------------------------------------------------- solve stage
@@ -182,13 +186,16 @@ __device__ void fdstage_body(const KParams& k, int li, double* B, int64_t ldb, i
   Mat<double> X = leaf_rhs(L, B, ldb);
   double* nv = k.nodeval + (int64_t)li * kw * k.R;
   leaf_sweep<T, HT, OP_L_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+  note_sweep(k, 1, L.type, A.m, m);
   if (L.type == LEAF_SINGLE) {
     leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    note_sweep(k, 1, L.type, A.m, m);
     return;
   }
   if (L.type == LEAF_MIDDLE) {
     // U sweep over G (left in place for the retrieval); keep only the tips
     leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), tdst(nv, nv + ku, 1, 1, kw, ku, m - kl, m), 0, nrhs, lds);
+    note_sweep(k, 1, L.type, A.m, m);
     return;
   }
   const int klf = A.kl, r0 = m - klf;
@@ -200,6 +207,7 @@ __device__ void fdstage_body(const KParams& k, int li, double* B, int64_t ldb, i
   }
   __syncthreads();
   wg_usweep<FNB, T>(A, Tm, nrhs, r0, lds);
+  note_sweep(k, 1, L.type, klf, m);
   for (int idx = threadIdx.x; idx < klf * nrhs; idx += NT) {
     int r = r0 + idx % klf, q = idx / klf;
     if (L.type == LEAF_FIRST) nv[(ku + (r - r0)) + (int64_t)q * kw] = Tm.at(r, q);
@@ -242,6 +250,7 @@ __device__ void fretrieve_body(const KParams& k, int li, double* B, int64_t ldb,
     // G_i -= L^{-1} [C^ X_{i-1,b}; 0; B^ X_{i+1,t}], then one full U sweep
     leaf_sweep<T, HT, OP_L_FWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, kl, m - ku, m), rhs_dst(X, m, 1), 0, nrhs, lds);
     leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    note_sweep(k, 1, L.type, A.m, m, 2);
     return;
   }
   const bool rev = L.type == LEAF_LAST;
@@ -261,6 +270,7 @@ __device__ void fretrieve_body(const KParams& k, int li, double* B, int64_t ldb,
   }
   (void)klf;
   leaf_sweep<T, HT, OP_U_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+  note_sweep(k, 1, L.type, A.m, m);
 }
 
 template <typename T, int HT>
@@ -274,6 +284,7 @@ __device__ void fzsweep_body(const KParams& k, int li, double* B, int64_t ldb, i
   if (L.type == LEAF_SINGLE) {
     leaf_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
     leaf_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    note_sweep(k, 2, L.type, A.m, m, 2);
     return;
   }
   double* scr = k.sscr + L.sscr_off;
@@ -284,11 +295,13 @@ __device__ void fzsweep_body(const KParams& k, int li, double* B, int64_t ldb, i
   // H = U^{-T} [0; F~; 0] into scratch
   leaf_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m, top0, m - klf), tdst(scr, nullptr, 1, 1, k.sscr_ld, m, m, m), 0,
                                nrhs, lds);
+  note_sweep(k, 2, L.type, A.m, m);
   if (L.type == LEAF_MIDDLE) {
     double* zprev = k.ztip + (int64_t)(li - 1) * kw * R;       // top_kl(Z_i)
     double* znext = k.ztip + (int64_t)li * kw * R + kl;        // bottom_ku(Z_i)
     leaf_sweep<T, HT, OP_LT_BWD>(A, dv, tsrc(scr, 1, 1, k.sscr_ld, 0, m), tdst(zprev, znext, 1, 1, kw, kl, m - ku, m),
                                  0, nrhs, lds);
+    note_sweep(k, 2, L.type, A.m, m);
     return;
   }
   const int rmin = m - kuf;
@@ -300,6 +313,7 @@ __device__ void fzsweep_body(const KParams& k, int li, double* B, int64_t ldb, i
   }
   __syncthreads();
   wg_ltsweep<FNB, T>(A, Tm, nrhs, rmin, lds);
+  note_sweep(k, 2, L.type, m - r0, m);
   if (!rev) {
     double* z = k.ztip + kl;
     for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
@@ -337,6 +351,7 @@ __device__ void fdtstage_body(const KParams& k, int li, double* B, int64_t ldb, 
     __syncthreads();
     leaf_sweep<T, HT, OP_UT_FWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
     leaf_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+    note_sweep(k, 2, L.type, A.m, m, 2);
     return;
   }
   const bool rev = L.type == LEAF_LAST;
@@ -351,6 +366,7 @@ __device__ void fdtstage_body(const KParams& k, int li, double* B, int64_t ldb, 
   }
   __syncthreads();
   wg_utsweep<FNB, T>(A, Tm, nrhs, r0, lds);
+  note_sweep(k, 2, L.type, klf, m);
   for (int idx = threadIdx.x; idx < m * nrhs; idx += NT) {
     int r = idx % m, q = idx / m;
     double v = S.at(r, q);
@@ -359,6 +375,7 @@ __device__ void fdtstage_body(const KParams& k, int li, double* B, int64_t ldb, 
   }
   __syncthreads();
   leaf_sweep<T, HT, OP_LT_BWD>(A, dv, rhs_src(X, m), rhs_dst(X, m), 0, nrhs, lds);
+  note_sweep(k, 2, L.type, A.m, m);
 }
 
 // ---------------------------------------------------------------- runners

@@ -34,6 +34,12 @@ int run_init_status(DevStatus* s, hipStream_t st) {
   return 0;
 }
 
+int run_zero_counters(unsigned long long* c, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, c, n);
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
 int run_gform_batch(const BatchArgs& ba, hipStream_t st, int nitems) {
   if (nitems <= 0) return 0;
   ProfScope ps("k_gform", st);

@@ -48,6 +48,18 @@ __device__ __forceinline__ bool solve_idle(const KParams& k) {
   return status_bad(k.status) || (k.skip != nullptr && *k.skip != 0);
 }
 
+// Counts one triangular sweep of one column set over `rows` of a partition
+// of m rows (stage and counter layout as KParams::sweeps).  Called by one
+// thread of one workgroup per partition.
+__device__ __forceinline__ void note_sweep(const KParams& k, int stage, int type, int rows, int m, int sets = 1) {
+  if (k.sweeps != nullptr && threadIdx.x == 0)
+    atomicAdd(&k.sweeps[(stage * 4 + type) * 2 + (rows >= m ? 1 : 0)], (unsigned long long)sets);
+}
+
+static __global__ void k_zero_counters(unsigned long long* c, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
+}
+
 static __global__ void k_init_status(DevStatus* s) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     s->zero_row = ULLONG_MAX;
@@ -184,6 +196,7 @@ __global__ __launch_bounds__(NT) void k_leaf_factor(KParams k) {
     }
     __syncthreads();
     wg_lsweep<NB, T>(A, make_mat(fs, (int64_t)1, (int64_t)m), ku, jv, lds);
+    note_sweep(k, 0, L.type, m - jv, m);
     return;
   }
   if (L.type == LEAF_MIDDLE) {
@@ -204,8 +217,12 @@ __global__ __launch_bounds__(NT) void k_leaf_factor(KParams k) {
     // W: full L sweep; V: L sweep truncated to where B^ (moved by at most kl
     // rows under pivoting) becomes nonzero; then one full U sweep over [V W].
     wg_lsweep<NB, T>(A, make_mat(fs + (int64_t)ku * m, (int64_t)1, (int64_t)m), kl, 0, lds);
-    wg_lsweep<NB, T>(A, make_mat(fs, (int64_t)1, (int64_t)m), ku, m - ku - (k.pivot ? kl : 0), lds);
+    const int vstart = m - ku - (k.pivot ? kl : 0);
+    wg_lsweep<NB, T>(A, make_mat(fs, (int64_t)1, (int64_t)m), ku, vstart, lds);
     wg_usweep<NB, T>(A, make_mat(fs, (int64_t)1, (int64_t)m), kw, 0, lds);
+    note_sweep(k, 0, L.type, m, m);                                   // W: L sweep
+    note_sweep(k, 0, L.type, m - (max(vstart, 0) / NB) * NB, m);      // V: truncated L sweep
+    note_sweep(k, 0, L.type, m, m, 2);                                // V and W: one U pass
     double* tp = tips.node(li);
     for (int idx = threadIdx.x; idx < kw * kw; idx += NT) {
       int r = idx % kw, c = idx / kw;
@@ -241,6 +258,7 @@ __global__ __launch_bounds__(NT) void k_leaf_factor(KParams k) {
     }
     __syncthreads();
     wg_lsweep<NB, T>(A, make_mat(fs, (int64_t)1, (int64_t)m), kuf, jstart, lds);
+    note_sweep(k, 0, L.type, m - jstart, m);
     T* sd = reinterpret_cast<T*>(k.side) + (rev ? (int64_t)k.side_ld * k.kmax : 0);
     for (int idx = threadIdx.x; idx < h * kuf; idx += NT) {
       int r = idx % h, c = idx / h;
@@ -248,6 +266,7 @@ __global__ __launch_bounds__(NT) void k_leaf_factor(KParams k) {
     }
     __syncthreads();
     wg_usweep<NB, T>(A, make_mat(fs, (int64_t)1, (int64_t)m), kuf, m - klf, lds);
+    note_sweep(k, 0, L.type, klf, m);
     if (!rev) {
       double* vb = tips.Vb(0);
       for (int idx = threadIdx.x; idx < kl * ku; idx += NT) {
@@ -346,8 +365,10 @@ __global__ __launch_bounds__(NT) void k_leaf_dstage(KParams k, double* B, int64_
   const int64_t sld = k.sscr_ld;
   double* nv = k.nodeval + (int64_t)li * kw * k.R;
   wg_lsweep<NB, T>(A, X, nrhs, 0, lds);
+  note_sweep(k, 1, L.type, m, m);
   if (L.type == LEAF_SINGLE) {
     wg_usweep<NB, T>(A, X, nrhs, 0, lds);
+    note_sweep(k, 1, L.type, m, m);
     return;
   }
   if (L.type == LEAF_MIDDLE) {
@@ -358,6 +379,7 @@ __global__ __launch_bounds__(NT) void k_leaf_dstage(KParams k, double* B, int64_
     }
     __syncthreads();
     wg_usweep<NB, T>(A, S, nrhs, 0, lds);
+    note_sweep(k, 1, L.type, m, m);
     for (int idx = threadIdx.x; idx < kw * nrhs; idx += NT) {
       int r = idx % kw, q = idx / kw;
       int fr = r < ku ? r : m - kl + (r - ku);
@@ -375,6 +397,7 @@ __global__ __launch_bounds__(NT) void k_leaf_dstage(KParams k, double* B, int64_
   }
   __syncthreads();
   wg_usweep<NB, T>(A, Tm, nrhs, r0, lds);
+  note_sweep(k, 1, L.type, klf, m);
   for (int idx = threadIdx.x; idx < klf * nrhs; idx += NT) {
     int r = r0 + idx % klf, q = idx / klf;
     if (L.type == LEAF_FIRST) nv[(ku + (r - r0)) + (int64_t)q * kw] = Tm.at(r, q);
@@ -478,6 +501,7 @@ __global__ __launch_bounds__(NT) void k_leaf_retrieve(KParams k, double* B, int6
     }
     __syncthreads();
     wg_usweep<NB, T>(A, X, nrhs, 0, lds);
+    note_sweep(k, 1, L.type, m, m, 2);
     return;
   }
   // first / last: subtract the stored side block times the neighbour value.
@@ -498,6 +522,7 @@ __global__ __launch_bounds__(NT) void k_leaf_retrieve(KParams k, double* B, int6
     wg_gemm_cols<T>(h, nrhs, kuf, -1.0, sd, 1, k.side_ld, xn, 1, kw, 1.0, &X.at(m - h, 0), X.rs, X.ld);
   }
   wg_usweep<NB, T>(A, X, nrhs, 0, lds);
+  note_sweep(k, 1, L.type, m, m);
 }
 
 // ===========================================================================
@@ -516,6 +541,7 @@ __global__ __launch_bounds__(NT) void k_leaf_zsweep(KParams k, double* B, int64_
   if (L.type == LEAF_SINGLE) {
     wg_utsweep<NB, T>(A, X, nrhs, 0, lds);
     wg_ltsweep<NB, T>(A, X, nrhs, 0, lds);
+    note_sweep(k, 2, L.type, m, m, 2);
     return;
   }
   double* scr = k.sscr + L.sscr_off;
@@ -533,8 +559,10 @@ __global__ __launch_bounds__(NT) void k_leaf_zsweep(KParams k, double* B, int64_
   }
   __syncthreads();
   wg_utsweep<NB, T>(A, S, nrhs, 0, lds);
+  note_sweep(k, 2, L.type, m, m);
   if (L.type == LEAF_MIDDLE) {
     wg_ltsweep<NB, T>(A, S, nrhs, 0, lds);
+    note_sweep(k, 2, L.type, m, m);
     double* zprev = k.ztip + (int64_t)(li - 1) * kw * R;   // b part: top_kl(Z_i)
     double* znext = k.ztip + (int64_t)li * kw * R + kl;    // t part: bottom_ku(Z_i)
     for (int idx = threadIdx.x; idx < kl * nrhs; idx += NT) {
@@ -558,6 +586,7 @@ __global__ __launch_bounds__(NT) void k_leaf_zsweep(KParams k, double* B, int64_
   }
   __syncthreads();
   wg_ltsweep<NB, T>(A, Tm, nrhs, rmin, lds);
+  note_sweep(k, 2, L.type, m - r0, m);
   if (!rev) {
     double* z = k.ztip + kl;   // interface 0, t part: bottom_ku(Z_1)
     for (int idx = threadIdx.x; idx < ku * nrhs; idx += NT) {
@@ -708,6 +737,7 @@ __global__ __launch_bounds__(NT) void k_leaf_dtstage(KParams k, double* B, int64
     __syncthreads();
     wg_utsweep<NB, T>(A, X, nrhs, 0, lds);
     wg_ltsweep<NB, T>(A, X, nrhs, 0, lds);
+    note_sweep(k, 2, L.type, m, m, 2);
     return;
   }
   // first / last: X = P^T L^{-T} (H + [0; U_bb^{-T} Y_b]), H kept in scratch.
@@ -732,6 +762,8 @@ __global__ __launch_bounds__(NT) void k_leaf_dtstage(KParams k, double* B, int64
   }
   __syncthreads();
   wg_ltsweep<NB, T>(A, X, nrhs, 0, lds);
+  note_sweep(k, 2, L.type, klf, m);
+  note_sweep(k, 2, L.type, m, m);
 }
 
 // ===========================================================================

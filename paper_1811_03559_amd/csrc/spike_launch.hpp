@@ -56,7 +56,15 @@ struct KParams {
   double* sdinv;         // 16 x 16 diagonal-block inverses of S's L and U, per interface
   int* sperm;            // row permutation of S's factorisation, per interface
   double* mtmp;          // reduced-solve scratch, kw x R per interface
+  // Instrumented sweep counts (nullptr: off): entry (stage * 4 + leaf type) * 2
+  // + full counts the triangular sweeps of one column set (a spike block or
+  // the right-hand sides) over one partition's factor, full = 1 when the
+  // sweep runs over all of the partition's rows; stage 0 = factorisation,
+  // 1 = A X = F, 2 = A^T X = F.
+  unsigned long long* sweeps;
 };
+
+constexpr int kSweepCounters = 3 * 4 * 2;
 
 // Work items of several systems in one launch (solve-stage batching).
 // System s owns the items [off[s], off[s+1]) of the launch; for a merge
@@ -124,6 +132,7 @@ int run_init_status(DevStatus* s, hipStream_t st);
 int run_gform(const KParams& k, hipStream_t st, const double* B, int64_t ldb, int nrhs);
 
 int launch_init_status(DevStatus* s, hipStream_t st);
+int run_zero_counters(unsigned long long* c, int n, hipStream_t st);
 int launch_phase_batch(const BatchArgs& ba, bool fp32, int ht, size_t lds, hipStream_t st, int phase, int nitems);
 int launch_mlevel_batch(const BatchArgs& ba, int mht, hipStream_t st, int nitems, bool trans, bool up);
 int launch_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);

@@ -284,6 +284,7 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
   pl.off_sdinv = take(8 * ((size_t)nif * ((ku + 15) / 16) * 512 + 512));
   pl.off_sperm = take(sizeof(int) * (size_t)nif * std::max(1, ku));
   pl.off_mtmp = take(8 * (size_t)nif * kw * R);
+  pl.off_sweeps = take(8 * 3 * 4 * 2);
   pl.off_kp = take(kKParamsBytes);
   if (pl.refine_enabled()) {
     pl.off_xacc = take(8 * (size_t)n * R);

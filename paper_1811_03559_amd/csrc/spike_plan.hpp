@@ -51,6 +51,7 @@ struct Plan {
   size_t off_nodeval = 0, off_st = 0, off_xint = 0, off_ztip = 0, off_crl = 0;
   size_t off_sscr = 0, off_xacc = 0, off_res = 0, off_colred = 0;
   size_t off_sdinv = 0, off_sperm = 0, off_mtmp = 0;
+  size_t off_sweeps = 0;           // instrumented sweep counters
   size_t off_kp = 0;               // device copy of the kernel parameter block
   size_t total = 0;
   size_t sscr_rows = 0;            // rows of solve scratch per leaf (max)

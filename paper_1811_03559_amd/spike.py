@@ -153,6 +153,10 @@ def lib():
             L.spike_autotune.restype = ctypes.c_int
             L.spike_autotune.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_i32, ctypes.POINTER(Opts),
                                          _c_p, _c_size, _c_p, _c_i64, _c_p, ctypes.POINTER(TuneResult)]
+            L.spike_sweep_counting.restype = ctypes.c_int
+            L.spike_sweep_counting.argtypes = [ctypes.c_int]
+            L.spike_sweep_counts.restype = ctypes.c_int
+            L.spike_sweep_counts.argtypes = [_c_p, ctypes.POINTER(ctypes.c_uint64)]
             L.spike_profile_enable.restype = ctypes.c_int
             L.spike_profile_enable.argtypes = [ctypes.c_int]
             L.spike_profile_report.restype = ctypes.c_int
@@ -323,6 +327,23 @@ class Factorization:
         return {"info": st.info, "n_boosts": st.n_boosts, "refine_iters": st.refine_iters,
                 "min_abs_pivot": st.min_abs_pivot, "berr": st.berr}
 
+    def sweep_counts(self):
+        """The handle's instrumented sweep counters (it must have been made
+        inside ``sweep_counting()``): a dict keyed by (stage, partition type,
+        full) with stage in ("factor", "solve", "solve_t"), type in ("single",
+        "first", "middle", "last") and full True for sweeps over all of a
+        partition's rows."""
+        buf = (ctypes.c_uint64 * 24)()
+        rc = lib().spike_sweep_counts(self.h, buf)
+        if rc != 0:
+            raise SpikeError("spike_sweep_counts", rc)
+        out = {}
+        for si, stage in enumerate(("factor", "solve", "solve_t")):
+            for ti, typ in enumerate(("single", "first", "middle", "last")):
+                for full in (0, 1):
+                    out[(stage, typ, bool(full))] = int(buf[(si * 4 + ti) * 2 + full])
+        return out
+
     def plan(self):
         info = PlanInfo()
         rc = lib().spike_handle_plan(self.h, ctypes.byref(info))
@@ -341,6 +362,19 @@ class Factorization:
             self.close()
         except Exception:
             pass
+
+
+class sweep_counting:
+    """Context manager: factorisations made inside it count their triangular
+    sweeps on the device (spike_sweep_counting)."""
+
+    def __enter__(self):
+        lib().spike_sweep_counting(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().spike_sweep_counting(0)
+        return False
 
 
 def levels_for(p: int) -> int:

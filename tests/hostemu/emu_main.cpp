@@ -9,7 +9,8 @@
 //
 // Usage: emu_main IN OUT.  IN holds int64 n, kl, ku, p, pivot, nrhs, trans,
 // then the band (n x (kl+ku+1), column-major LAPACK storage) and F (n x
-// nrhs, column-major); OUT receives int64 info followed by X.
+// nrhs, column-major); OUT receives int64 info, X, then the 24 sweep
+// counters of the run (the layout of KParams::sweeps).
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -242,6 +243,8 @@ int main(int argc, char** argv) {
   k.sdinv = static_cast<double*>(R.at(pl.off_sdinv));
   k.sperm = static_cast<int*>(R.at(pl.off_sperm));
   k.mtmp = static_cast<double*>(R.at(pl.off_mtmp));
+  std::vector<unsigned long long> sweeps(kSweepCounters, 0ull);
+  k.sweeps = sweeps.data();
 
   LaunchCfg c;
   c.nb = pl.nb;
@@ -267,6 +270,7 @@ int main(int argc, char** argv) {
   FILE* g = std::fopen(argv[2], "wb");
   std::fwrite(&info, 8, 1, g);
   std::fwrite(B.data(), 8, B.size(), g);
+  std::fwrite(sweeps.data(), 8, sweeps.size(), g);
   std::fclose(g);
   std::printf("replay: n=%lld kl=%d ku=%d p=%d pivot=%d nrhs=%d trans=%d nb=%d info=%lld\n", (long long)n, kl, ku,
               pl.p, pivot, nrhs, (int)trans, pl.nb, (long long)info);

@@ -56,9 +56,10 @@ def build(workdir: str | None = None) -> str:
 
 
 def run(exe: str, ab: np.ndarray, kl: int, ku: int, F: np.ndarray, p: int, pivot: bool, trans: bool,
-        timeout: float = 600.0):
+        timeout: float = 600.0, sweeps: bool = False):
     """Factor and solve on the CPU replay.  ab: (n, kl+ku+1) band rows in the
-    binding's layout; F: (nrhs, n).  Returns (info, X with F's shape)."""
+    binding's layout; F: (nrhs, n).  Returns (info, X with F's shape), or
+    (info, X, sweep counters) with sweeps=True."""
     n = ab.shape[0]
     F = np.atleast_2d(F)
     nrhs = F.shape[0]
@@ -76,4 +77,7 @@ def run(exe: str, ab: np.ndarray, kl: int, ku: int, F: np.ndarray, p: int, pivot
     out = np.fromfile(fout, dtype=np.float64)
     info = int(out[:1].view(np.int64)[0])
     shutil.rmtree(work, ignore_errors=True)
-    return info, out[1:].reshape(nrhs, n)
+    X = out[1:1 + n * nrhs].reshape(nrhs, n)
+    if sweeps:
+        return info, X, out[1 + n * nrhs:].view(np.uint64).astype(np.int64)
+    return info, X

@@ -77,3 +77,32 @@ def test_non_pivoting_generic_path(exe, trans):
     info, X = replay.run(exe, ab, kl, ku, F, p=p, pivot=False, trans=trans)
     assert info == 0
     _check(ab, kl, ku, F, X, trans)
+
+
+@pytest.mark.parametrize("pivot", [False, True])
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_sweep_counts_match_paper_table(exe, pivot, trans, nrhs):
+    """Table tab:sweeps of section "Optimizing per-partition costs": the
+    factorisation does no full sweep on the first and last partitions and 3 on
+    a middle one, the solve 2 and 4 (the transpose solve the same, as the
+    transpose section states); counted by the workgroup kernels themselves."""
+    import sweep_table
+    n, kl, ku, p = 1200, 6, 4, 5
+    ab = inputs.band_dominant(n, kl, ku, inputs.rng_for(91))
+    F = inputs.rhs(n, nrhs, inputs.rng_for(92))
+    info, X, cnt = replay.run(exe, ab, kl, ku, F, p=p, pivot=pivot, trans=trans, sweeps=True)
+    assert info == 0
+    _check(ab, kl, ku, F, X, trans)
+    counts = sweep_table.from_array(cnt)
+    sweep_table.check(counts, p, stages=("factor", "solve_t" if trans else "solve"))
+    assert counts[("solve" if trans else "solve_t", "middle", True)] == 0
+    # the truncated sweeps of the first and last partitions are there too
+    assert counts[("factor", "first", False)] == 2 and counts[("factor", "last", False)] == 2
+
+
+def test_sweep_table_is_the_papers():
+    """The golden file holds the paper's values (a mistyped table would make
+    the counter test above compare against the wrong numbers)."""
+    import sweep_table
+    assert sweep_table.table() == {"first_last": (0, 2), "middle": (3, 4)}
