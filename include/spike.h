@@ -135,8 +135,11 @@ SPIKE_API void spike_default_opts(spike_opts *opts);
  * sizes is not NULL, the p partition sizes (int64) in order.  sizes must hold
  * at least p entries when opts->p > 0, else 4096.  Touches no device.
  * Errors: -1 n < 0, -2 kl < 0, -3 ku < 0, -4 bad opts (p < 0, p > n, a
- * partition smaller than kl+ku, an unknown mode, or with tree 1 a p that is
- * not 2^m + r with r <= 2^m - 2). */
+ * partition smaller than kl+ku, an unknown mode, with tree 1 a p that is
+ * not 2^m + r with r <= 2^m - 2, or partial pivoting with bandwidths too wide
+ * for 32-column panels in 128 KiB of LDS, i.e. when 32 (32 + max(kl,ku)) +
+ * 32 (kl + ku) elements of the factor precision exceed 128 KiB: in FP64
+ * with kl = ku, max(kl,ku) > 160). */
 SPIKE_API int spike_plan_query(int64_t n, int32_t kl, int32_t ku, const spike_opts *opts,
                      spike_plan_info *out, int64_t *sizes);
 

@@ -74,7 +74,7 @@ static int choose_p(int64_t n, int kl, int ku) {
   return (int)std::max<int64_t>(1, p);
 }
 
-int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
+int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl, bool narrow_pivot_panels) {
   if (o.p < 0 || (o.pivot != 0 && o.pivot != 1) || (o.precision != 0 && o.precision != 1) ||
       (o.sizing != 0 && o.sizing != 1) || (o.tree != 0 && o.tree != 1) || o.nrhs_max < 0 ||
       o.nrhs_hint < 0)
@@ -136,6 +136,7 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl) {
     if (leaf_lds_elems(nb, pl.kmax, kuw_max) * pl.tsize <= 128 * 1024) { pl.nb = nb; break; }
   }
   if (pl.nb == 0) return -4;   // bandwidth beyond the leaf kernels' LDS budget
+  if (o.pivot && pl.nb < kPivotMinPanel && !narrow_pivot_panels) return -4;
   pl.leaf_lds = leaf_lds_elems(pl.nb, pl.kmax, kuw_max) * pl.tsize + 2048;
   int kd = std::max(1, ku);   // interface LU is dense of order ku
   pl.nb_dense = 0;

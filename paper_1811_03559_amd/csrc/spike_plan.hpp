@@ -68,8 +68,16 @@ constexpr size_t kKParamsBytes = 1024;
 void default_opts(spike_opts *o);
 
 // Builds the plan.  Returns 0, or -4 for inconsistent options / sizes
-// (argument codes -1..-3 are checked by the caller).
-int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &plan);
+// (argument codes -1..-3 are checked by the caller).  Partial pivoting is
+// limited to bandwidths whose leaf kernels fit 32-column panels (about
+// max(kl, ku) <= 160 with kl = ku; see kPivotMinPanel); narrow_pivot_panels
+// lifts that limit for host-side replays of the kernels only.
+int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &plan, bool narrow_pivot_panels = false);
+
+// Narrowest panel of the partial-pivoting leaf kernels the library runs.
+// The workgroup LU with 16-column panels (pivoting, bandwidths above ~160)
+// faulted the GPU once with no cause shown, so it is not launched.
+constexpr int kPivotMinPanel = 32;
 
 // R13 of the load-balancing section (first/last size over inner size).
 double ratio_r13(double K, double nrhs_over_k);

@@ -187,7 +187,7 @@ int main(int argc, char** argv) {
   o.pivot = pivot;
   o.nrhs_max = std::max(1, nrhs);
   Plan pl;
-  if (make_plan(n, kl, ku, o, pl)) return 3;
+  if (make_plan(n, kl, ku, o, pl, /*narrow_pivot_panels=*/true)) return 3;
   Regions R = carve(pl);
 
   KParams k;

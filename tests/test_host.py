@@ -289,3 +289,17 @@ def test_factor_argument_errors_need_no_device():
     st = spike.Status()
     assert L.spike_info(None, ctypes.byref(st)) == -1
     assert L.spike_destroy(None) == -1
+
+
+def test_pivoting_limited_to_32_column_panels():
+    """The planner refuses partial pivoting where the leaf kernels would need
+    16-column panels (FP64, kl = ku > 160), and accepts it up to 160 and for
+    every non-pivoting bandwidth the engines serve."""
+    n = 50000
+    assert spike.plan_query(n, 160, 160, p=8, pivot=True)["p"] == 8
+    assert spike.plan_query(n, 200, 200, p=8)["p"] == 8
+    with pytest.raises(spike.SpikeError) as e:
+        spike.plan_query(n, 200, 200, p=8, pivot=True)
+    assert e.value.code == -4
+    # FP32 factors halve the LDS per element: 32-column panels still fit
+    assert spike.plan_query(n, 200, 200, p=8, pivot=True, precision="mixed")["p"] == 8
