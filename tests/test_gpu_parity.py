@@ -294,8 +294,10 @@ def test_refinement_unequal_bands(kl, ku, trans, nrhs):
     i) and the transposed backward error uses ||A||_1; nrhs = 12 selects the
     16-wide residual kernel."""
     n, p = 7001, 5
+    # + 1 on the diagonal: with kl = 0 or ku = 0 an end row has no
+    # off-diagonal entries, and a pure multiple of its abs-sum would be zero
     ab = inputs.band_dominant(n, kl, ku, inputs.rng_for(inputs.seed_for(3, 10 * kl + ku)),
-                              diag_mult_range=(1.01, 1.5))
+                              diag_mult_range=(1.01, 1.5), diag_add=1.0)
     X_true = inputs.rhs(n, nrhs, inputs.rng_for(kl + 3 * ku + nrhs))
     F = oracle.gbmv(ab, kl, ku, X_true, trans=trans)
     X, info, _ = run(ab, kl, ku, F, trans=trans, p=p, precision="mixed")
