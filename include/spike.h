@@ -213,6 +213,26 @@ typedef struct spike_kernel_time {
 SPIKE_API int spike_profile_enable(int on);
 SPIKE_API int spike_profile_report(spike_kernel_time *out, int cap, int *count);
 
+/* Factorisation without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same as spike_factor, but the
+ * factorisation lives in the library's own device scratch array of
+ * spike_scratch_capacity() bytes (64 MiB), one copy per GPU, held from the
+ * library's load until the process ends; the call allocates no device
+ * memory.  Every call on one GPU shares that GPU's array: a later call
+ * overwrites the factorisation an earlier handle on the same GPU points to
+ * (use or destroy earlier handles first), and calls that overlap on one GPU
+ * race.  The handle is used with spike_solve, spike_solve_transpose,
+ * spike_info and spike_destroy as usual; with precision 1 dAB must stay
+ * valid while it is used.
+ * Errors: -1..-5 as spike_factor, -6 bad opts, -7 the factorisation needs
+ * more than spike_scratch_capacity() bytes (spike_workspace_size reports
+ * the need), -8 out NULL, -1000-hipError (the scratch address or a launch). */
+SPIKE_API size_t spike_scratch_capacity(void);
+SPIKE_API int spike_factor_scratch(int64_t n, int32_t kl, int32_t ku, const double *dAB,
+                                   int64_t ldab, const spike_opts *opts, hipStream_t stream,
+                                   spike_handle *out);
+
 /* Instrumented sweep counts, the measurement behind Table tab:sweeps of
  * section "Optimizing per-partition costs" (full triangular sweeps per
  * partition in the factorisation and solve stages; the transpose section

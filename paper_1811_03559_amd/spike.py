@@ -153,6 +153,11 @@ def lib():
             L.spike_autotune.restype = ctypes.c_int
             L.spike_autotune.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_i32, ctypes.POINTER(Opts),
                                          _c_p, _c_size, _c_p, _c_i64, _c_p, ctypes.POINTER(TuneResult)]
+            L.spike_scratch_capacity.restype = _c_size
+            L.spike_scratch_capacity.argtypes = []
+            L.spike_factor_scratch.restype = ctypes.c_int
+            L.spike_factor_scratch.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, ctypes.POINTER(Opts), _c_p,
+                                               ctypes.POINTER(_c_p)]
             L.spike_sweep_counting.restype = ctypes.c_int
             L.spike_sweep_counting.argtypes = [ctypes.c_int]
             L.spike_sweep_counts.restype = ctypes.c_int
@@ -284,7 +289,10 @@ class Factorization:
     """A SPIKE factorisation resident in a device workspace.
 
     ``ab``: float64 CUDA tensor (n, ldab), LAPACK band storage.  The tensor is
-    kept referenced (mixed precision reads it for residuals)."""
+    kept referenced (mixed precision reads it for residuals).  ``workspace``:
+    a uint8 CUDA tensor, None (one is allocated), or "scratch": the library's
+    own per-GPU scratch array (spike_factor_scratch, no allocation; a later
+    "scratch" factorisation on the same GPU overwrites this one)."""
 
     def __init__(self, ab, kl, ku, *, stream=None, workspace=None, **opts):
         import torch
@@ -294,6 +302,17 @@ class Factorization:
         self.opts = make_opts(**opts)
         self.nrhs_max = self.opts.nrhs_max
         need = workspace_size(self.n, kl, ku, **opts)
+        if isinstance(workspace, str):
+            if workspace != "scratch":
+                raise ValueError("workspace must be a tensor, None or 'scratch'")
+            self.ab, self.ws, self.device = ab, None, ab.device
+            h = ctypes.c_void_p()
+            rc = lib().spike_factor_scratch(self.n, self.kl, self.ku, ctypes.c_void_p(ab.data_ptr()), self.ldab,
+                                            ctypes.byref(self.opts), _stream_handle(stream), ctypes.byref(h))
+            if rc != 0:
+                raise SpikeError("spike_factor_scratch", rc)
+            self.h = h
+            return
         if workspace is None:
             workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=ab.device)
         if workspace.numel() < need:
