@@ -14,8 +14,11 @@ the timed region.
 
 Prints one JSON line (rank 0, one GPU).  Extra fields: `roofline` for the
 kernel that takes the most time in a step, `cpu_baseline` (the FP64 oracle
-on the host, a bounded sample scaled to the full size) and `detail`
-(per-phase times, solve GB/s, nrhs = 64 solves, residuals).
+on one host core at the full size, factorisation and solves timed apart,
+with the host's CPU model and core count) and `detail` (per-kernel and
+per-phase times, solve GB/s, nrhs = 64 solves, residuals, agreement with the
+oracle's solutions, and the other workloads: the small n = 4096 system,
+partition counts and sizings, pivoting, mixed precision, serving).
 """
 import argparse
 import json
@@ -127,7 +130,7 @@ def step_work(sizes, k, nrhs):
         "k_ftip_w": {"flops": 2.0 * mid * k * k, "engine": "mfma"},
         "k_ftip_u": {"flops": 4.0 * mid * k * k, "engine": "mfma"},
         "k_mgemm": {"flops": f_gemm, "engine": "mfma"},
-        "k_mlu": {"flops": f_lu, "engine": "mfma"},
+        "k_mlu": {"flops": f_lu, "engine": "alu"},   # pivot search and rank-1 steps on the VALU
         "k_mtrsm": {"flops": f_trsm, "engine": "mfma"},
         "k_fdstage": {"bytes": sweep},
         "k_fretrieve": {"bytes": sweep},
@@ -206,20 +209,40 @@ def roofline(name, work, timing, workload):
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "work_per_step": work["bytes"]}
 
 
-def cpu_baseline(k, n_full, n_sample=150_000):
+def host_cpu():
+    """Model name and core counts of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "logical_cpus": os.cpu_count()}
+
+
+def cpu_baseline(ab, kl, ku, F):
+    """The oracle (plain FP64 banded GE, non-pivoting LU) on one host core at
+    the full headline size: one factorisation, then A X = F and A^T X = F,
+    timed apart."""
     import oracle
-    from paper_1811_03559_amd import inputs
-    ab, kl, ku, F = inputs.cfg1(n=n_sample, k=k, nrhs=1)
     oracle.build()
     t0 = time.perf_counter()
-    oracle.gbsv_nt(ab, kl, ku, F, pivot=False)
-    dt = time.perf_counter() - t0
-    t_full = dt * n_full / n_sample          # banded GE cost is linear in n
-    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": ("FP64 banded GE (non-pivoting LU, one factorisation, then A X = F and "
-                       "A^T X = F), single thread, on the first %d rows' recipe (n=%d, k=%d, nrhs=1): "
-                       "%.2f s, scaled linearly to n=%d" % (n_sample, n_sample, k, dt, n_full)),
-            "sample_seconds": dt}
+    info, w, ipiv = oracle.gbtrf(ab, kl, ku, pivot=False)
+    t1 = time.perf_counter()
+    X = oracle.gbtrs(w, ipiv, kl, ku, F, pivot=False)
+    t2 = time.perf_counter()
+    Xt = oracle.gbtrs(w, ipiv, kl, ku, F, pivot=False, trans=True)
+    t3 = time.perf_counter()
+    del w
+    total = t3 - t0
+    return {"value": 1.0 / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": ("the full step at n=%d, kl=ku=%d, nrhs=1 (FP64 banded GE without pivoting: one "
+                       "factorisation, then A X = F and A^T X = F), single thread" % (ab.shape[0], kl)),
+            "factor_s": t1 - t0, "solve_s": t2 - t1, "solve_t_s": t3 - t2, "info": info,
+            "host": host_cpu(), "_x": (X, Xt)}
 
 
 def _ev():
@@ -246,17 +269,58 @@ def fwd_err(X, Xt):
     return float(np.abs(X - Xt).max() / np.abs(Xt).max())
 
 
+def inputs_rhs64(n):
+    from paper_1811_03559_amd import inputs
+    return inputs.rhs(n, 64, inputs.rng_for(inputs.seed_for(1, 1)))
+
+
+def bench_cfg0(reps=20):
+    """The small configuration (n = 4096, kl = ku = 4, p = 3, nrhs = 1):
+    latency-bound, so factor and solve times in microseconds."""
+    import torch
+    import oracle
+    from paper_1811_03559_amd import inputs, spike
+    ab, kl, ku, Xt = inputs.cfg0()
+    F = oracle.gbmv(ab, kl, ku, Xt)
+    dab = torch.from_numpy(ab).cuda()
+    dF = torch.from_numpy(F).cuda()
+    ws = torch.empty(spike.workspace_size(ab.shape[0], kl, ku, p=3), dtype=torch.uint8, device="cuda")
+    holder = {}
+
+    def fac():
+        if "f" in holder:
+            holder["f"].close()
+        holder["f"] = spike.Factorization(dab, kl, ku, p=3, workspace=ws)
+    fac()
+    torch.cuda.synchronize()
+    t_f = _timed(fac, reps)
+    B = dF.clone()
+    t_n = _timed(lambda: (B.copy_(dF), holder["f"].solve_(B)), reps)
+    t_t = _timed(lambda: (B.copy_(dF), holder["f"].solve_(B, trans=True)), reps)
+    B.copy_(dF)
+    holder["f"].solve_(B)
+    X = B.cpu().numpy()
+    out = {"n": ab.shape[0], "kl": kl, "ku": ku, "p": 3, "factor_us": t_f * 1e3, "solve_us": t_n * 1e3,
+           "solve_t_us": t_t * 1e3, "relres": oracle.relres(ab, kl, ku, X, F),
+           "vs_oracle": oracle.fwd_err(X, oracle.gbsv(ab, kl, ku, F, pivot=False))}
+    holder["f"].close()
+    return out
+
+
 def bench_p_sweep(dab, ab, k, F, ps=(250, 500)):
     """Factor and N/T solve times of the headline system at other partition
     counts (equal sizes; balanced merge tree and the paper's 2^m + r layout)
-    and with R13 sizing at p = 256."""
+    and with R13 sizing at p = 256, 250 and 500; nrhs = 1 N and T, and
+    nrhs = 64 N."""
     import torch
     from paper_1811_03559_amd import spike
     out = {}
     dF = torch.from_numpy(F).cuda()
     cases = [(pp, "equal", "balanced") for pp in ps] + [(pp, "equal", "paper") for pp in ps]
-    for p, sizing, tree in cases + [(256, "r13", "balanced")]:
-        opts = dict(p=p, sizing=sizing, nrhs_hint=1, tree=tree)
+    cases += [(pp, "r13", "balanced") for pp in (256,) + tuple(ps)]
+    F64 = torch.from_numpy(inputs_rhs64(F.shape[1])).cuda()
+    for p, sizing, tree in cases:
+        opts = dict(p=p, sizing=sizing, nrhs_hint=1, tree=tree, nrhs_max=64)
         holder = {}
 
         def fac():
@@ -266,9 +330,11 @@ def bench_p_sweep(dab, ab, k, F, ps=(250, 500)):
         B, Bt = dF.clone(), dF.clone()
         t_n = _timed(lambda: f.solve_(B))
         t_t = _timed(lambda: f.solve_(Bt, trans=True))
+        B64 = F64.clone()
+        t_64 = _timed(lambda: f.solve_(B64))
         out["p%d_%s%s" % (p, sizing, "_paper_tree" if tree == "paper" else "")] = {
             "levels": spike.plan_query(ab.shape[0], k, k, **opts)["levels"],
-            "factor_ms": t_f, "solve_ms": t_n, "solve_t_ms": t_t,
+            "factor_ms": t_f, "solve_ms": t_n, "solve_t_ms": t_t, "solve_ms_nrhs64": t_64,
             "step_ms": t_f + t_n + t_t,
             "sizes_first_mid": spike.plan_query(ab.shape[0], k, k, **opts)["sizes"][:2],
             "relres_n": relres(ab, k, k, B.cpu().numpy()[0], F[0]),
@@ -289,7 +355,10 @@ def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
     F = np.stack([band_matvec(ab, kl, ku, Xtrue[j]) for j in range(nrhs)])
     dab = torch.from_numpy(ab).cuda()
     dF = torch.from_numpy(F).cuda()
-    out = {"n": n, "k": k, "nrhs": nrhs}
+    import oracle
+    t0 = time.perf_counter()
+    kappa = oracle.cond1(ab, kl, ku)
+    out = {"n": n, "k": k, "nrhs": nrhs, "oracle_kappa1": kappa, "oracle_kappa1_s": time.perf_counter() - t0}
     for p in ps:
         row = {}
         for label, opts in (("pivoting", dict(pivot=True)), ("non_pivoting", dict(pivot=False)),
@@ -398,16 +467,22 @@ def bench_serving(nreq=1024, budget_gib=64, pool_per_bucket=4, seed=None):
         t1 = time.perf_counter()
         st = srv.stats()
         srv.close()
+        import oracle
         worst = {"dom_fp64": 0.0, "dom_mixed": 0.0, "piv": 0.0}
+        lat = {"dom_fp64": [], "dom_mixed": [], "piv": []}
         for i, r in enumerate(reqs):
+            key = "piv" if r["cls"] == "piv" else "dom_" + r["precision"]
+            if sts[i]["state"] == 2:
+                lat[key].append(sts[i]["latency_s"])
             if not check[i] or sts[i]["state"] != 2:
                 continue
             ab = mats[(r["cls"], r["k"], r["member"])][0]
             X = Bs[i][:2].cpu().numpy()
-            e = max(relres(ab, r["k"], r["k"], X[j], Fs[i][j], trans=r["trans"])
+            e = max(oracle.relres(ab, r["k"], r["k"], X[j], Fs[i][j], trans=r["trans"])
                     for j in range(min(2, r["nrhs"])))
-            key = "piv" if r["cls"] == "piv" else "dom_" + r["precision"]
             worst[key] = max(worst[key], e)
+        by_class = {c: {"requests": len(v), "p50_ms": float(np.percentile(v, 50)) * 1e3 if v else None,
+                        "p99_ms": float(np.percentile(v, 99)) * 1e3 if v else None} for c, v in lat.items()}
         print("[bench] serving rate=%s: %d done in %.2f s" % (rate, st["completed"], t1 - t0),
               file=sys.stderr, flush=True)
         return {"requests": len(reqs), "failed": st["failed"], "completed": st["completed"],
@@ -415,7 +490,7 @@ def bench_serving(nreq=1024, budget_gib=64, pool_per_bucket=4, seed=None):
                 "p50_ms": st["p50_s"] * 1e3, "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
                 "factorizations": st["factorizations"], "evictions": st["evictions"],
                 "hbm_high_water_gib": st["hbm_high_water"] / 2.0 ** 30,
-                "checked": int(sum(check)), "max_relres": worst}
+                "checked": int(sum(check)), "max_relres": worst, "by_class": by_class}
 
     burst = run(None)
     theta = burst["solves_per_s"]
@@ -551,6 +626,8 @@ def main():
         del B64
         def note(msg):
             print("[bench] %s (%.1f s)" % (msg, time.perf_counter() - t_start), file=sys.stderr, flush=True)
+        note("cfg0")
+        detail["cfg0"] = bench_cfg0()
         if "psweep" in secs:
             note("p sweep")
             detail["p_sweep"] = bench_p_sweep(dab, ab, k, F)
@@ -580,7 +657,15 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(k, n)
+        print("[bench] cpu baseline (oracle, one core, full size) (%.1f s)" % (time.perf_counter() - t_start),
+              file=sys.stderr, flush=True)
+        cb = cpu_baseline(ab, kl, ku, F)
+        Xo, Xot = cb.pop("_x")
+        out["cpu_baseline"] = cb
+        # the GPU step's solutions against the oracle's, element by element
+        if "relres_n" in detail:
+            detail["vs_oracle_n"] = fwd_err(X, Xo[0])
+            detail["vs_oracle_t"] = fwd_err(Xt, Xot[0])
     out["detail"] = detail
     print(json.dumps(out), flush=True)
 

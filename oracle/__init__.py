@@ -54,6 +54,8 @@ def _load():
             lib.orc_gbsv_nt.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _p, _p, _i64]
             lib.orc_gbtrf.restype = _i64
             lib.orc_gbtrf.argtypes = [_i64, _int, _int, _p, _i64, _int, _p, _p]
+            lib.orc_gbtrs.restype = None
+            lib.orc_gbtrs.argtypes = [_i64, _int, _int, _p, _p, _int, _int, _int, _p, _i64]
             lib.orc_gbmv.restype = None
             lib.orc_gbmv.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _p, _i64, _p, _i64]
             lib.orc_gbnorm.restype = _dbl
@@ -120,6 +122,19 @@ def gbtrf(ab, kl, ku, pivot=True):
     info = _load().orc_gbtrf(n, kl, ku, ab.ctypes.data, ldab, int(bool(pivot)),
                              w.ctypes.data, ipiv.ctypes.data)
     return int(info), w, ipiv
+
+
+def gbtrs(w, ipiv, kl, ku, F, pivot=True, trans=False):
+    """Solve op(A) X = F with the factors (w, ipiv) of gbtrf (same pivot
+    flag); F as (nrhs, n) or (n,)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int64)
+    n = w.shape[0]
+    squeeze = np.ndim(F) == 1
+    X = _rhs(F, n)
+    _load().orc_gbtrs(n, kl, ku, w.ctypes.data, ipiv.ctypes.data, int(bool(pivot)), int(bool(trans)),
+                      X.shape[0], X.ctypes.data, max(n, 1))
+    return X[0] if squeeze else X
 
 
 def gbmv(ab, kl, ku, X, trans=False):

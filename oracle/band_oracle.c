@@ -250,6 +250,25 @@ ORC_EXPORT int64_t orc_gbtrf(int64_t n, int kl, int ku, const double *ab,
     return info;
 }
 
+/* Solve op(A) X = F in place on B with the factors orc_gbtrf returned (w:
+ * working band of ld 2kl+ku+1 when pivoting, else kl+ku+1; ipiv: its
+ * pivots), the same substitutions as orc_gbsv.  Lets a caller time the
+ * factorisation and the solves apart. */
+ORC_EXPORT void orc_gbtrs(int64_t n, int kl, int ku, const double *w,
+                          const int64_t *ipiv, int pivot, int trans, int nrhs,
+                          double *B, int64_t ldb) {
+    work_band b;
+    b.n = n;
+    b.kl = kl;
+    b.uw = pivot ? kl + ku : ku;
+    b.ldw = (int64_t)kl + b.uw + 1;
+    b.w = (double *)w;
+    for (int c = 0; c < nrhs; ++c) {
+        if (trans) solve_t(&b, pivot ? ipiv : NULL, B + (int64_t)c * ldb);
+        else       solve_n(&b, pivot ? ipiv : NULL, B + (int64_t)c * ldb);
+    }
+}
+
 /* Y = op(A) X (trans 0: A, 1: A^T), plain summation in index order. */
 ORC_EXPORT void orc_gbmv(int64_t n, int kl, int ku, const double *ab,
                          int64_t ldab, int trans, int nrhs, const double *X,

@@ -376,3 +376,21 @@ def test_singular_coupling_makes_elimination_meet_a_zero_pivot():
         for pivot in (False, True):
             with pytest.raises(ZeroDivisionError):
                 oracle.gbsv(ab, 1, 1, np.ones((1, n)), pivot=pivot)
+
+
+@pytest.mark.parametrize("kl,ku", [(0, 2), (3, 3), (5, 1)])
+@pytest.mark.parametrize("pivot", [False, True])
+@pytest.mark.parametrize("trans", [False, True])
+def test_gbtrf_then_gbtrs_is_gbsv(kl, ku, pivot, trans):
+    """Factor once (orc_gbtrf) and solve with the stored factors (orc_gbtrs):
+    bitwise the one-call solve, and the dense solution to rounding."""
+    n = 77
+    ab = rand_band(n, kl, ku, 50 + kl + 3 * ku, dominant=not pivot)
+    F = inputs.rhs(n, 2, inputs.rng_for(51))
+    info, w, ipiv = oracle.gbtrf(ab, kl, ku, pivot=pivot)
+    assert info == 0
+    X = oracle.gbtrs(w, ipiv, kl, ku, F, pivot=pivot, trans=trans)
+    np.testing.assert_array_equal(X, oracle.gbsv(ab, kl, ku, F, pivot=pivot, trans=trans))
+    A = dense_from_band(ab, kl, ku)
+    ref = np.linalg.solve(A.T if trans else A, F.T).T
+    assert oracle.fwd_err(X, ref) <= 1e-14 * np.linalg.cond(A, 1) * n
