@@ -347,8 +347,11 @@ def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
     """Pivoting SPIKE next to non-pivoting SPIKE (with boosting) on the
     ill-conditioned N(0,1) row-scaled band: errors against the manufactured
     solution, residuals, FP64 refinement of the pivoting factors (<= 3
-    steps), and the boosted non-pivoting factors used as a preconditioner
-    for FP64 refinement (<= 10 steps)."""
+    steps), the boosted non-pivoting factors used as a preconditioner for
+    FP64 refinement (<= 10 steps), and both factorisations as right
+    preconditioners of GMRES(30) (<= 150 Arnoldi steps; `refine_iters`
+    then counts the Arnoldi steps and `berr` is GMRES's final backward
+    error)."""
     import torch
     from paper_1811_03559_amd import inputs, spike
     ab, kl, ku, Xtrue = inputs.cfg2(n=n, k=k, nrhs=nrhs)
@@ -363,7 +366,8 @@ def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
         row = {}
         for label, opts in (("pivoting", dict(pivot=True)), ("non_pivoting", dict(pivot=False)),
                             ("pivoting_refined", dict(pivot=True, max_refine=3)),
-                            ("boosted_refined", dict(pivot=False, max_refine=10))):
+                            ("boosted_refined", dict(pivot=False, max_refine=10)),
+                            ("pivoting_gmres", dict(pivot=True)), ("boosted_gmres", dict(pivot=False))):
             holder = {}
 
             def fac():
@@ -371,9 +375,16 @@ def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
             t_f = _timed(fac)
             f = holder["f"]
             B = dF.clone()
-            t_s = _timed(lambda: f.solve_(B))
+            gm = {}
+            if label.endswith("gmres"):
+                t_s = _timed(lambda: gm.update(f.solve_gmres_(B, restart=30, max_iters=150)))
+            else:
+                t_s = _timed(lambda: f.solve_(B))
             X = B.cpu().numpy()
             info = f.info()
+            if gm:
+                info["refine_iters"] = gm["iters"]
+                info["berr"] = gm["berr"]
             row[label] = {"factor_ms": t_f, "solve_ms": t_s,
                           "relres": max(relres(ab, kl, ku, X[j], F[j]) for j in range(0, nrhs, 5)),
                           "fwd_err": fwd_err(X, Xtrue), "n_boosts": info["n_boosts"],

@@ -213,6 +213,51 @@ typedef struct spike_kernel_time {
 SPIKE_API int spike_profile_enable(int on);
 SPIKE_API int spike_profile_report(spike_kernel_time *out, int cap, int *count);
 
+/* Restarted GMRES with the factorisation as preconditioner (a project
+ * addition to the paper's boosting scheme: diagonal boosting perturbs the
+ * factors, and the paper corrects with an outer iteration, section "An
+ * efficient pivoting scheme"; GMRES is the Krylov form of that correction,
+ * more robust than refinement when many pivots were boosted).  Solves
+ * op(A) X = F in FP64 with the caller's band A (the dAB given to
+ * spike_factor, which must still be valid) and the handle's factors M as a
+ * right preconditioner: op(A) M^{-1} u = F, X = M^{-1} u, restarted every
+ * `restart` Arnoldi steps (classical Gram-Schmidt, reorthogonalised once),
+ * until the backward error ||F - op(A) X||_inf / (||op(A)||_inf ||X||_inf)
+ * of every column is <= tol or max_iters steps were taken.
+ *   h, nrhs, dB, ldb, trans  as spike_solve / spike_solve_transpose;
+ *                            nrhs <= the handle's nrhs_max
+ *   opts       NULL for the defaults [restart 30, max_iters 300, tol 1e-13]
+ *   dWork      device scratch of work_bytes >= spike_krylov_workspace_size,
+ *              256-byte aligned (holds the basis: about (restart + 7) n nrhs
+ *              doubles)
+ *   out        iterations, restarts, whether every column converged, and
+ *              the final backward error (max over columns)
+ * Blocks the host until done (each Arnoldi step reads its Hessenberg column).
+ * Returns 0 (see out->converged), 1 when the factorisation reported
+ * info != 0 (dB untouched), -1 bad handle, -2 nrhs < 0 or > nrhs_max, -3
+ * dB NULL, -4 ldb < n, -6 bad opts, -7 dWork NULL or misaligned, -8
+ * work_bytes too small, -11 out NULL, -1000-hipError. */
+typedef struct spike_krylov_opts {
+    int32_t restart;      /* basis vectors before a restart (1..500)     [30] */
+    int32_t max_iters;    /* cap on Arnoldi steps over all restarts     [300] */
+    double tol;           /* backward-error target                    [1e-13] */
+} spike_krylov_opts;
+
+typedef struct spike_krylov_result {
+    int32_t iters;        /* Arnoldi steps taken                              */
+    int32_t restarts;     /* restart cycles completed                         */
+    int32_t converged;    /* 1 when every column met tol                      */
+    double berr;          /* final backward error, max over columns (NaN if a
+                             residual or solution became non-finite)        */
+} spike_krylov_result;
+
+SPIKE_API void spike_krylov_default_opts(spike_krylov_opts *opts);
+SPIKE_API int spike_krylov_workspace_size(spike_handle h, int32_t nrhs, const spike_krylov_opts *opts,
+                                          size_t *bytes);
+SPIKE_API int spike_solve_gmres(spike_handle h, int32_t nrhs, double *dB, int64_t ldb, int32_t trans,
+                                const spike_krylov_opts *opts, void *dWork, size_t work_bytes,
+                                hipStream_t stream, spike_krylov_result *out);
+
 /* Factorisation without a caller workspace, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same as spike_factor, but the

@@ -11,6 +11,7 @@
 #include "../../include/spike.h"
 #include "spike_launch.hpp"
 #include "spike_plan.hpp"
+#include "spike_krylov.hpp"
 #include "spike_refine.hpp"
 
 namespace {
@@ -446,6 +447,62 @@ int spike_info(spike_handle h, spike_status* out) {
   std::memcpy(&mp, &s.min_pivot_bits, sizeof(mp));
   out->min_abs_pivot = mp;
   out->berr = s.berr;
+  return 0;
+}
+
+void spike_krylov_default_opts(spike_krylov_opts* o) {
+  if (!o) return;
+  o->restart = 30;
+  o->max_iters = 300;
+  o->tol = 1e-13;
+}
+
+namespace {
+bool krylov_opts_ok(const spike_krylov_opts& o) {
+  return o.restart >= 1 && o.restart <= 500 && o.max_iters >= 0 && o.tol > 0.0;
+}
+}  // namespace
+
+int spike_krylov_workspace_size(spike_handle h, int32_t nrhs, const spike_krylov_opts* opts, size_t* bytes) {
+  if (!valid(h)) return -1;
+  if (nrhs < 0 || nrhs > h->plan.nrhs_max) return -2;
+  spike_krylov_opts o;
+  spike_krylov_default_opts(&o);
+  if (opts) o = *opts;
+  if (!krylov_opts_ok(o)) return -3;
+  if (!bytes) return -4;
+  *bytes = spike::gmres_workspace_bytes(h->plan.n, nrhs, o.restart);
+  return 0;
+}
+
+int spike_solve_gmres(spike_handle h, int32_t nrhs, double* dB, int64_t ldb, int32_t trans,
+                      const spike_krylov_opts* opts, void* dWork, size_t work_bytes, hipStream_t stream,
+                      spike_krylov_result* out) {
+  if (!valid(h)) return -1;
+  if (nrhs < 0 || nrhs > h->plan.nrhs_max) return -2;
+  const int64_t n = h->plan.n;
+  if (nrhs > 0 && n > 0 && dB == nullptr) return -3;
+  if (ldb < (n > 1 ? n : 1)) return -4;
+  spike_krylov_opts o;
+  spike_krylov_default_opts(&o);
+  if (opts) o = *opts;
+  if (!krylov_opts_ok(o)) return -6;
+  if (!out) return -11;
+  std::memset(out, 0, sizeof(*out));
+  if (nrhs == 0 || n == 0) {
+    out->converged = 1;
+    return 0;
+  }
+  if (dWork == nullptr || (reinterpret_cast<uintptr_t>(dWork) & 255u) != 0) return -7;
+  if (work_bytes < spike::gmres_workspace_bytes(n, nrhs, o.restart)) return -8;
+  spike::GmresResult r{};
+  const int e = spike::gmres_solve(h->kp, h->cfg, h->plan, static_cast<char*>(dWork), stream, dB, ldb, nrhs,
+                                   trans != 0, o.restart, o.max_iters, o.tol, &r);
+  if (e) return e;
+  out->iters = r.iters;
+  out->restarts = r.restarts;
+  out->converged = r.converged;
+  out->berr = r.berr;
   return 0;
 }
 

@@ -300,6 +300,29 @@ int prepare_refine(const KParams& k, const Plan& pl, char*, hipStream_t st) {
   return chk();
 }
 
+int launch_anorm(const KParams& k, int64_t n, int kl, int ku, hipStream_t st) {
+  const int64_t blocks = (n + RT - 1) / RT;
+  ProfScope ps("k_anorm", st);
+  hipLaunchKernelGGL(k_anorm, dim3((unsigned)blocks), dim3(RT), 0, st, k.dAB, k.ldab, n, kl, ku, k.status);
+  return chk();
+}
+
+int launch_residual(const KParams& k, int64_t n, int kl, int ku, const double* F, const double* X, int64_t ldx,
+                    double* R, int64_t ld, int nrhs, bool trans, unsigned long long* colred, const int32_t* skip,
+                    hipStream_t st) {
+  const unsigned rblocks = (unsigned)((n + RT - 1) / RT);
+  ProfScope ps(trans ? "k_residual_t" : "k_residual_n", st);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(rblocks), dim3(RT), 0, st, k.dAB, k.ldab, n, kl, ku, F, X, ldx, R, ld, nrhs,
+                       colred, skip);
+  };
+  if (nrhs == 1) trans ? go(k_residual<1, true>) : go(k_residual<1, false>);
+  else if (nrhs <= 8) trans ? go(k_residual<8, true>) : go(k_residual<8, false>);
+  else if (nrhs <= 16) trans ? go(k_residual<16, true>) : go(k_residual<16, false>);
+  else trans ? go(k_residual<32, true>) : go(k_residual<32, false>);
+  return chk();
+}
+
 int refined_solve(const KParams& k, const LaunchCfg& c, const Plan& pl, char* ws, hipStream_t st, double* B,
                   int64_t ldb, int nrhs, bool trans) {
   const int64_t n = pl.n;

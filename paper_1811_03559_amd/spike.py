@@ -54,6 +54,14 @@ class TuneResult(ctypes.Structure):
                 ("candidates", _c_i32)]
 
 
+class KrylovOpts(ctypes.Structure):
+    _fields_ = [("restart", _c_i32), ("max_iters", _c_i32), ("tol", _c_dbl)]
+
+
+class KrylovResult(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("restarts", _c_i32), ("converged", _c_i32), ("berr", _c_dbl)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", _c_size), ("max_inflight", _c_i32), ("streams", _c_i32),
                 ("batch_window", _c_i32), ("dpool", _c_p)]
@@ -153,6 +161,14 @@ def lib():
             L.spike_autotune.restype = ctypes.c_int
             L.spike_autotune.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_i32, ctypes.POINTER(Opts),
                                          _c_p, _c_size, _c_p, _c_i64, _c_p, ctypes.POINTER(TuneResult)]
+            L.spike_krylov_default_opts.restype = None
+            L.spike_krylov_default_opts.argtypes = [ctypes.POINTER(KrylovOpts)]
+            L.spike_krylov_workspace_size.restype = ctypes.c_int
+            L.spike_krylov_workspace_size.argtypes = [_c_p, _c_i32, ctypes.POINTER(KrylovOpts),
+                                                      ctypes.POINTER(_c_size)]
+            L.spike_solve_gmres.restype = ctypes.c_int
+            L.spike_solve_gmres.argtypes = [_c_p, _c_i32, _c_p, _c_i64, _c_i32, ctypes.POINTER(KrylovOpts), _c_p,
+                                            _c_size, _c_p, ctypes.POINTER(KrylovResult)]
             L.spike_scratch_capacity.restype = _c_size
             L.spike_scratch_capacity.argtypes = []
             L.spike_factor_scratch.restype = ctypes.c_int
@@ -337,6 +353,29 @@ class Factorization:
         if rc != 0:
             raise SpikeError("spike_solve_transpose" if trans else "spike_solve", rc)
         return B
+
+    def solve_gmres_(self, B, *, trans=False, restart=30, max_iters=300, tol=1e-13, stream=None):
+        """In-place GMRES solve of op(A) X = B with this factorisation as the
+        right preconditioner (spike_solve_gmres; blocks until done).  Returns
+        a dict with iters, restarts, converged and berr; raises SpikeError
+        with code 1 when the factorisation failed (B untouched)."""
+        import torch
+        B = _check_rhs(B, self.n)
+        ldb = B.stride(0) if B.shape[0] > 1 else max(self.n, 1)
+        o = KrylovOpts(int(restart), int(max_iters), float(tol))
+        need = _c_size()
+        rc = lib().spike_krylov_workspace_size(self.h, int(B.shape[0]), ctypes.byref(o), ctypes.byref(need))
+        if rc != 0:
+            raise SpikeError("spike_krylov_workspace_size", rc)
+        ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device=B.device)
+        res = KrylovResult()
+        rc = lib().spike_solve_gmres(self.h, int(B.shape[0]), ctypes.c_void_p(B.data_ptr()), int(ldb),
+                                     1 if trans else 0, ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel(), _stream_handle(stream), ctypes.byref(res))
+        if rc != 0:
+            raise SpikeError("spike_solve_gmres", rc)
+        return {"iters": res.iters, "restarts": res.restarts, "converged": bool(res.converged),
+                "berr": res.berr}
 
     def info(self):
         st = Status()

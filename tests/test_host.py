@@ -153,7 +153,8 @@ def test_workspace_grows_with_problem():
 _STRUCTS = [("spike_opts", "Opts"), ("spike_status", "Status"), ("spike_plan_info", "PlanInfo"),
             ("spike_kernel_time", "KernelTime"), ("spike_tune_result", "TuneResult"),
             ("spike_server_opts", "ServerOpts"), ("spike_request", "Request"),
-            ("spike_request_status", "RequestStatus"), ("spike_server_report", "ServerReport")]
+            ("spike_request_status", "RequestStatus"), ("spike_server_report", "ServerReport"),
+            ("spike_krylov_opts", "KrylovOpts"), ("spike_krylov_result", "KrylovResult")]
 
 
 def test_ctypes_structs_match_the_c_layout(tmp_path):
