@@ -394,6 +394,42 @@ def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
     return out
 
 
+def bench_complex(n=500_000, k=80, nrhs=1, p=256):
+    """A complex band of half the headline order with half its bandwidth
+    (its real embedding is n = 10^6 with 161 sub- and superdiagonals, the
+    headline's size), diagonally dominant, FP64 and FP32 factors with
+    refinement: factorisation and A, A^T, A^H solves, residuals from the
+    complex oracle's product."""
+    import torch
+    import oracle
+    from paper_1811_03559_amd import inputs, spike
+    rng = inputs.rng_for(inputs.seed_for(5))
+    ab = inputs.zband_dominant(n, k, k, rng, diag_mult=1.05)
+    Xt = inputs.zrhs(n, nrhs, rng)
+    out = {"n": n, "k": k, "nrhs": nrhs, "p": p}
+    dab = torch.from_numpy(ab).cuda()
+    for label, opts in (("fp64", {}), ("mixed", dict(precision="mixed"))):
+        holder = {}
+
+        def fac():
+            holder["f"] = spike.ZFactorization(dab, k, k, p=p, nrhs_max=max(nrhs, 1), **opts)
+        t_f = _timed(fac)
+        f = holder["f"]
+        row = {"factor_ms": t_f}
+        for trans in ("N", "T", "C"):
+            F = oracle.zgbmv(ab, k, k, Xt, trans=trans)
+            dF = torch.from_numpy(F).cuda()
+            B = dF.clone()
+            row["solve_%s_ms" % trans] = _timed(lambda: (B.copy_(dF), f.solve_(B, trans=trans)))
+            X = B.cpu().numpy()
+            row["relres_%s" % trans] = oracle.zrelres(ab, k, k, X, F, trans=trans)
+            row["fwd_err_%s" % trans] = fwd_err(X, Xt)
+        row["info"] = f.info()
+        f.close()
+        out[label] = row
+    return out
+
+
 def bench_mixed(n=1_000_000, k=128, nrhs=32, p=256):
     """FP32 block factors and tips with FP64 reduced system, residual and
     refinement, against plain FP64, both to a backward error of 1e-13."""
@@ -522,8 +558,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-detail", action="store_true",
                     help="skip every detail section (phase times and the other workloads)")
-    ap.add_argument("--sections", default="psweep,pivoting,mixed,serving",
-                    help="detail sections: psweep, pivoting, mixed, serving")
+    ap.add_argument("--sections", default="psweep,pivoting,mixed,complex,serving",
+                    help="detail sections: psweep, pivoting, mixed, complex, serving")
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
@@ -651,6 +687,10 @@ def main():
         if "mixed" in secs:
             note("mixed precision")
             detail["mixed_precision"] = bench_mixed()
+            torch.cuda.empty_cache()
+        if "complex" in secs:
+            note("complex")
+            detail["complex"] = bench_complex()
             torch.cuda.empty_cache()
         if "serving" in secs:
             note("serving")

@@ -213,6 +213,44 @@ typedef struct spike_kernel_time {
 SPIKE_API int spike_profile_enable(int on);
 SPIKE_API int spike_profile_report(spike_kernel_time *out, int cap, int *count);
 
+/* Complex banded systems (the complex precisions of the paper's library,
+ * section "Introduction": double complex, and single complex through
+ * precision 1, FP32 factors with FP64 refinement).  A complex band A
+ * (kl, ku) acts on interleaved unknowns like the real 2n x 2n band with
+ * 2 x 2 blocks [[Re a, -Im a], [Im a, Re a]] (2 kl + 1 sub- and 2 ku + 1
+ * superdiagonals), and the factorisation is the SPIKE factorisation of that
+ * real band, built on the device from the complex one.  Its transpose is
+ * the band of A^H, so the same factors solve A^H z = f directly and
+ * A^T z = f as A^H conj(z) = conj(f).  Each row j is first multiplied by
+ * the unit-modulus conj(a_jj) / |a_jj| (the factors are those of D A, D
+ * unitary and diagonal), which makes the diagonal real and positive: for a
+ * diagonally dominant A the non-pivoting elimination of the embedding then
+ * meets no small pivots inside its 2 x 2 blocks.
+ *   dAB   device complex band, LAPACK zgb layout with interleaved real and
+ *         imaginary doubles: A(i,j) = dAB[2 ((ku + i - j) + j ldab)] +
+ *         i dAB[2 ((ku + i - j) + j ldab) + 1], ldab >= kl + ku + 1 (in
+ *         complex elements).  Read during spike_zfactor only (the
+ *         refinement residual of precision 1 reads the embedded real band,
+ *         which lives in dWork).
+ *   opts  as spike_factor, for the real embedding (partition sizes, p,
+ *         pivoting and precision refer to it: p partitions of the 2n real
+ *         rows; a zero-pivot info i refers to real row i, complex row
+ *         (i + 1) / 2)
+ *   dWork device, work_bytes >= spike_zworkspace_size, 256-byte aligned.
+ * spike_zsolve: dB device complex n x nrhs, interleaved, column-major with
+ * leading dimension ldb (in complex elements, >= n), overwritten with the
+ * solution of op(A) Z = F: trans 0 = A, 1 = A^T, 2 = A^H.  The handle is
+ * used with spike_info and spike_destroy as usual.
+ * Errors: as spike_factor / spike_solve; spike_zsolve -1 also for a handle
+ * that is not complex, -5 a bad trans. */
+SPIKE_API int spike_zworkspace_size(int64_t n, int32_t kl, int32_t ku, const spike_opts *opts,
+                                    size_t *bytes);
+SPIKE_API int spike_zfactor(int64_t n, int32_t kl, int32_t ku, const double *dAB, int64_t ldab,
+                            const spike_opts *opts, void *dWork, size_t work_bytes,
+                            hipStream_t stream, spike_handle *out);
+SPIKE_API int spike_zsolve(spike_handle h, int32_t nrhs, double *dB, int64_t ldb, int32_t trans,
+                           hipStream_t stream);
+
 /* Restarted GMRES with the factorisation as preconditioner (a project
  * addition to the paper's boosting scheme: diagonal boosting perturbs the
  * factors, and the paper corrects with an outer iteration, section "An

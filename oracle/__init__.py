@@ -2,8 +2,8 @@
 
 A thin ctypes wrapper over ``band_oracle.c``: plain FP64 banded Gaussian
 elimination (with and without partial pivoting) for ``A X = F`` and
-``A^T X = F``, banded products, residual metrics and a 1-norm condition
-estimate.  Only ``tests/``, the smoke check and the CPU-baseline leg of the
+``A^T X = F``, in real and in complex arithmetic (``A^H`` too), banded
+products, residual metrics and a 1-norm condition estimate.  Only ``tests/``, the smoke check and the CPU-baseline leg of the
 benchmark use it.  The solver library never imports it, and it imports
 nothing from the solver library.
 
@@ -56,6 +56,12 @@ def _load():
             lib.orc_gbtrf.argtypes = [_i64, _int, _int, _p, _i64, _int, _p, _p]
             lib.orc_gbtrs.restype = None
             lib.orc_gbtrs.argtypes = [_i64, _int, _int, _p, _p, _int, _int, _int, _p, _i64]
+            lib.orc_zgbsv.restype = _i64
+            lib.orc_zgbsv.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _int, _p, _i64]
+            lib.orc_zgbmv.restype = None
+            lib.orc_zgbmv.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _p, _i64, _p, _i64]
+            lib.orc_zrelres.restype = _dbl
+            lib.orc_zrelres.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _p, _i64, _p, _i64]
             lib.orc_gbmv.restype = None
             lib.orc_gbmv.argtypes = [_i64, _int, _int, _p, _i64, _int, _int, _p, _i64, _p, _i64]
             lib.orc_gbnorm.restype = _dbl
@@ -171,6 +177,57 @@ def cond1(ab, kl, ku):
 def r13(K, nrhs_over_k):
     """Load-balancing ratio R13 = n1/n3 of the paper's load-balancing section."""
     return _load().orc_r13(float(K), float(nrhs_over_k))
+
+
+_ZTRANS = {False: 0, True: 1, "N": 0, "T": 1, "C": 2, 0: 0, 1: 1, 2: 2}
+
+
+def _zband(ab, kl, ku):
+    ab = np.ascontiguousarray(ab, dtype=np.complex128)
+    n, ldab = ab.shape
+    if ldab < kl + ku + 1:
+        raise ValueError("ldab too small")
+    return ab, n, ldab
+
+
+def _zrhs(F, n):
+    F = np.array(F, dtype=np.complex128, order="C", copy=True)
+    if F.ndim == 1:
+        F = F[None, :]
+    if F.shape[1] != n:
+        raise ValueError("rhs must have shape (nrhs, n)")
+    return F
+
+
+def zgbsv(ab, kl, ku, F, pivot=True, trans="N"):
+    """Complex band solve: op(A) Z = F with trans "N", "T" (A^T) or "C"
+    (A^H); ab complex (n, ldab) in the real band's layout, F (nrhs, n)."""
+    ab, n, ldab = _zband(ab, kl, ku)
+    squeeze = np.ndim(F) == 1
+    X = _zrhs(F, n)
+    info = _load().orc_zgbsv(n, kl, ku, ab.ctypes.data, ldab, int(bool(pivot)), _ZTRANS[trans],
+                             X.shape[0], X.ctypes.data, max(n, 1))
+    if info != 0:
+        raise ZeroDivisionError("oracle factorisation info=%d" % info)
+    return X[0] if squeeze else X
+
+
+def zgbmv(ab, kl, ku, X, trans="N"):
+    ab, n, ldab = _zband(ab, kl, ku)
+    squeeze = np.ndim(X) == 1
+    Xc = _zrhs(X, n)
+    Y = np.zeros_like(Xc)
+    _load().orc_zgbmv(n, kl, ku, ab.ctypes.data, ldab, _ZTRANS[trans], Xc.shape[0], Xc.ctypes.data,
+                      max(n, 1), Y.ctypes.data, max(n, 1))
+    return Y[0] if squeeze else Y
+
+
+def zrelres(ab, kl, ku, X, F, trans="N"):
+    ab, n, ldab = _zband(ab, kl, ku)
+    Xc = _zrhs(X, n)
+    Fc = _zrhs(F, n)
+    return _load().orc_zrelres(n, kl, ku, ab.ctypes.data, ldab, _ZTRANS[trans], Xc.shape[0], Xc.ctypes.data,
+                               max(n, 1), Fc.ctypes.data, max(n, 1))
 
 
 def fwd_err(X, Xref):

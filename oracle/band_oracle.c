@@ -32,6 +32,7 @@
  * Compile with: gcc -O2 -ffp-contract=off -shared -fPIC (no FMA contraction,
  * so every product and sum rounds as written).
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -399,4 +400,208 @@ ORC_EXPORT double orc_gbcond1(int64_t n, int kl, int ku, const double *ab,
 ORC_EXPORT double orc_r13(double K, double nrhs_over_k) {
     double r = nrhs_over_k;
     return 1.0 / (1.0 + K * r) + (1.5 + 2.0 * r) / (1.0 / K + r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Complex bands (double complex; the library's interleaved re/im layout is  */
+/* the memory layout of a double complex array): the same textbook banded   */
+/* elimination in complex arithmetic.  Partial pivoting takes the first row  */
+/* of maximal |Re| + |Im| among rows j..j+kl (LAPACK's choice for complex    */
+/* pivots).                                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    int kl, uw;
+    int64_t ldw;
+    double complex *w;
+} zwork_band;
+
+static double complex *zref(const zwork_band *b, int64_t i, int64_t j) {
+    return &b->w[(b->uw + i - j) + j * b->ldw];
+}
+
+static double cabs1(double complex z) { return fabs(creal(z)) + fabs(cimag(z)); }
+
+static int make_zwork_band(zwork_band *b, int64_t n, int kl, int ku,
+                           const double complex *ab, int64_t ldab, int pivot) {
+    b->n = n;
+    b->kl = kl;
+    b->uw = pivot ? kl + ku : ku;
+    b->ldw = (int64_t)kl + b->uw + 1;
+    b->w = (double complex *)calloc((size_t)(b->ldw * (n > 0 ? n : 1)), sizeof(double complex));
+    if (!b->w) return -1;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = imax64(0, j - ku); i <= imin64(n - 1, j + kl); ++i)
+            *zref(b, i, j) = ab[(ku + i - j) + j * ldab];
+    return 0;
+}
+
+static int64_t zlu(zwork_band *b, int64_t *ipiv) {
+    const int64_t n = b->n;
+    int64_t info = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t last_row = imin64(n - 1, j + b->kl);
+        int64_t last_col = imin64(n - 1, j + b->uw);
+        if (ipiv) {
+            int64_t r = j;
+            double best = cabs1(*zref(b, j, j));
+            for (int64_t i = j + 1; i <= last_row; ++i) {
+                double v = cabs1(*zref(b, i, j));
+                if (v > best) { best = v; r = i; }
+            }
+            ipiv[j] = r;
+            if (*zref(b, r, j) == 0.0) {
+                if (info == 0) info = j + 1;
+                continue;
+            }
+            if (r != j)
+                for (int64_t c = j; c <= last_col; ++c) {
+                    double complex t = *zref(b, j, c);
+                    *zref(b, j, c) = *zref(b, r, c);
+                    *zref(b, r, c) = t;
+                }
+        } else if (*zref(b, j, j) == 0.0) {
+            return j + 1;
+        }
+        double complex piv = *zref(b, j, j);
+        for (int64_t i = j + 1; i <= last_row; ++i) {
+            double complex l = *zref(b, i, j) / piv;
+            *zref(b, i, j) = l;
+            for (int64_t c = j + 1; c <= last_col; ++c)
+                *zref(b, i, c) -= l * *zref(b, j, c);
+        }
+    }
+    return info;
+}
+
+/* x <- op(A)^{-1} x; trans 0: A, 1: A^T, 2: A^H. */
+static void zsolve(const zwork_band *b, const int64_t *ipiv, int trans, double complex *x) {
+    const int64_t n = b->n;
+    if (trans == 0) {
+        for (int64_t j = 0; j < n; ++j) {
+            if (ipiv && ipiv[j] != j) { double complex t = x[j]; x[j] = x[ipiv[j]]; x[ipiv[j]] = t; }
+            for (int64_t i = j + 1; i <= imin64(n - 1, j + b->kl); ++i)
+                x[i] -= *zref(b, i, j) * x[j];
+        }
+        for (int64_t j = n - 1; j >= 0; --j) {
+            x[j] /= *zref(b, j, j);
+            for (int64_t i = imax64(0, j - b->uw); i < j; ++i)
+                x[i] -= *zref(b, i, j) * x[j];
+        }
+        return;
+    }
+    const int cj = trans == 2;
+    for (int64_t j = 0; j < n; ++j) {
+        double complex s = x[j];
+        for (int64_t i = imax64(0, j - b->uw); i < j; ++i) {
+            double complex u = *zref(b, i, j);
+            s -= (cj ? conj(u) : u) * x[i];
+        }
+        double complex d = *zref(b, j, j);
+        x[j] = s / (cj ? conj(d) : d);
+    }
+    for (int64_t j = n - 1; j >= 0; --j) {
+        double complex s = x[j];
+        for (int64_t i = j + 1; i <= imin64(n - 1, j + b->kl); ++i) {
+            double complex l = *zref(b, i, j);
+            s -= (cj ? conj(l) : l) * x[i];
+        }
+        x[j] = s;
+        if (ipiv && ipiv[j] != j) { double complex t = x[j]; x[j] = x[ipiv[j]]; x[ipiv[j]] = t; }
+    }
+}
+
+/* Solve op(A) Z = F in place on B (complex n x nrhs, column-major, ldb >= n);
+ * trans 0: A, 1: A^T, 2: A^H.  Returns 0, an argument error, or the 1-based
+ * index of the first zero pivot (B untouched). */
+ORC_EXPORT int64_t orc_zgbsv(int64_t n, int kl, int ku, const double complex *ab,
+                             int64_t ldab, int pivot, int trans, int nrhs,
+                             double complex *B, int64_t ldb) {
+    if (n < 0) return -1;
+    if (kl < 0) return -2;
+    if (ku < 0) return -3;
+    if (ldab < (int64_t)kl + ku + 1) return -5;
+    if (trans < 0 || trans > 2) return -7;
+    if (ldb < (n > 1 ? n : 1)) return -10;
+    if (n == 0) return 0;
+    zwork_band b;
+    if (make_zwork_band(&b, n, kl, ku, ab, ldab, pivot)) return -100;
+    int64_t *ipiv = pivot ? (int64_t *)malloc((size_t)n * sizeof(int64_t)) : NULL;
+    int64_t info = zlu(&b, ipiv);
+    if (info == 0)
+        for (int c = 0; c < nrhs; ++c) zsolve(&b, ipiv, trans, B + (int64_t)c * ldb);
+    free(ipiv);
+    free(b.w);
+    return info;
+}
+
+/* Y = op(A) X for complex bands (trans 0: A, 1: A^T, 2: A^H), plain
+ * summation in index order. */
+ORC_EXPORT void orc_zgbmv(int64_t n, int kl, int ku, const double complex *ab,
+                          int64_t ldab, int trans, int nrhs, const double complex *X,
+                          int64_t ldx, double complex *Y, int64_t ldy) {
+    for (int c = 0; c < nrhs; ++c) {
+        const double complex *x = X + (int64_t)c * ldx;
+        double complex *y = Y + (int64_t)c * ldy;
+        for (int64_t i = 0; i < n; ++i) {
+            double complex s = 0.0;
+            if (trans == 0) {
+                for (int64_t j = imax64(0, i - kl); j <= imin64(n - 1, i + ku); ++j)
+                    s += ab[(ku + i - j) + j * ldab] * x[j];
+            } else {
+                for (int64_t j = imax64(0, i - ku); j <= imin64(n - 1, i + kl); ++j) {
+                    double complex a = ab[(ku + j - i) + i * ldab];
+                    s += (trans == 2 ? conj(a) : a) * x[j];
+                }
+            }
+            y[i] = s;
+        }
+    }
+}
+
+/* max_c ||F_c - op(A) Z_c||_inf / (||op(A)||_inf ||Z_c||_inf) with the
+ * modulus as the entry norm; residual entries with compensated summation of
+ * the real and imaginary parts. */
+ORC_EXPORT double orc_zrelres(int64_t n, int kl, int ku, const double complex *ab,
+                              int64_t ldab, int trans, int nrhs,
+                              const double complex *X, int64_t ldx,
+                              const double complex *F, int64_t ldf) {
+    double anorm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        if (trans == 0)
+            for (int64_t j = imax64(0, i - kl); j <= imin64(n - 1, i + ku); ++j)
+                s += cabs(ab[(ku + i - j) + j * ldab]);
+        else
+            for (int64_t j = imax64(0, i - ku); j <= imin64(n - 1, i + kl); ++j)
+                s += cabs(ab[(ku + j - i) + i * ldab]);
+        if (s > anorm) anorm = s;
+    }
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        const double complex *x = X + (int64_t)c * ldx;
+        const double complex *f = F + (int64_t)c * ldf;
+        double rmax = 0.0, xmax = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double sr = creal(f[i]), si = cimag(f[i]), cr = 0.0, ci = 0.0;
+            int64_t lo = trans ? imax64(0, i - ku) : imax64(0, i - kl);
+            int64_t hi = trans ? imin64(n - 1, i + kl) : imin64(n - 1, i + ku);
+            for (int64_t j = lo; j <= hi; ++j) {
+                double complex a = trans ? ab[(ku + j - i) + i * ldab] : ab[(ku + i - j) + j * ldab];
+                if (trans == 2) a = conj(a);
+                double complex p = a * x[j];
+                double tr = -creal(p) - cr, t = sr + tr;
+                cr = (t - sr) - tr; sr = t;
+                double ti = -cimag(p) - ci, u = si + ti;
+                ci = (u - si) - ti; si = u;
+            }
+            double r = hypot(sr, si);
+            if (r > rmax) rmax = r;
+            if (cabs(x[i]) > xmax) xmax = cabs(x[i]);
+        }
+        double denom = anorm * xmax;
+        double rel = denom > 0.0 ? rmax / denom : (rmax > 0.0 ? INFINITY : 0.0);
+        if (rel > worst) worst = rel;
+    }
+    return worst;
 }

@@ -51,7 +51,7 @@ def units() -> list[tuple[str, str, list[str]]]:
     for ht in HTS:
         u.append((f"mfast_{ht}.o", "spike_inst.hip", ["-DSPIKE_INST_MFAST", f"-DSPIKE_HT={ht}"]))
     u.append(("common.o", "spike_inst.hip", ["-DSPIKE_INST_COMMON"]))
-    for src in ("spike_dispatch.hip", "spike_refine.hip", "spike_krylov.hip", "spike_scratch.hip", "spike_plan.cpp", "spike_api.cpp",
+    for src in ("spike_dispatch.hip", "spike_refine.hip", "spike_krylov.hip", "spike_complex.hip", "spike_scratch.hip", "spike_plan.cpp", "spike_api.cpp",
                 "spike_profile.cpp", "spike_server.cpp"):
         u.append((src.rsplit(".", 1)[0] + ".o", src, []))
     return u

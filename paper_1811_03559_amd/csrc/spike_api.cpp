@@ -41,7 +41,17 @@ struct spike_handle_s {
   char* ws;
   spike::KParams kp;
   spike::LaunchCfg cfg;
+  int64_t zn = -1;   // complex order when the handle holds a complex system's real embedding
+  double* zd = nullptr;   // its row rotations d_j (interleaved complex, in the workspace)
 };
+
+namespace spike {
+int launch_zembed(const double* zab, int64_t ldab, int64_t n, int kl, int ku, double* R, int64_t ldr, double* Dv,
+                  hipStream_t st);
+int launch_zrowscale(double* B, int64_t ldb2, int64_t n, int nrhs, const double* Dv, bool conj_d,
+                     const DevStatus* status, hipStream_t st);
+int launch_zconj(double* B, int64_t ldb2, int64_t n, int nrhs, const DevStatus* status, hipStream_t st);
+}  // namespace spike
 
 namespace {
 
@@ -504,6 +514,80 @@ int spike_solve_gmres(spike_handle h, int32_t nrhs, double* dB, int64_t ldb, int
   out->converged = r.converged;
   out->berr = r.berr;
   return 0;
+}
+
+namespace {
+// Bytes of the embedded real band and the row rotations at the front of a
+// complex workspace.
+size_t zband_bytes(int64_t n, int32_t kl, int32_t ku) {
+  const int64_t ldr = 2 * (int64_t)kl + 2 * (int64_t)ku + 3;
+  return ((size_t)(2 * n * ldr * 8) + 255) / 256 * 256;
+}
+size_t zrot_bytes(int64_t n) { return ((size_t)(16 * (n > 0 ? n : 1)) + 255) / 256 * 256; }
+}  // namespace
+
+int spike_zworkspace_size(int64_t n, int32_t kl, int32_t ku, const spike_opts* opts, size_t* bytes) {
+  if (n < 0) return -1;
+  if (kl < 0) return -2;
+  if (ku < 0) return -3;
+  size_t real = 0;
+  const int r = spike_workspace_size(2 * n, 2 * kl + 1, 2 * ku + 1, opts, &real);
+  if (r) return r < -3 ? r : -4;
+  if (bytes) *bytes = zband_bytes(n, kl, ku) + zrot_bytes(n) + real;
+  return 0;
+}
+
+int spike_zfactor(int64_t n, int32_t kl, int32_t ku, const double* dAB, int64_t ldab, const spike_opts* opts,
+                  void* dWork, size_t work_bytes, hipStream_t stream, spike_handle* out) {
+  if (n < 0) return -1;
+  if (kl < 0) return -2;
+  if (ku < 0) return -3;
+  if (dAB == nullptr && n > 0) return -4;
+  if (ldab < (int64_t)kl + ku + 1) return -5;
+  size_t need = 0;
+  if (spike_zworkspace_size(n, kl, ku, opts, &need)) return -6;
+  if (dWork == nullptr || (reinterpret_cast<uintptr_t>(dWork) & 255u) != 0) return -7;
+  if (work_bytes < need) return -8;
+  if (out == nullptr) return -10;
+  const int klr = 2 * kl + 1, kur = 2 * ku + 1;
+  const int64_t ldr = (int64_t)klr + kur + 1;
+  double* R = static_cast<double*>(dWork);
+  double* Dv = reinterpret_cast<double*>(static_cast<char*>(dWork) + zband_bytes(n, kl, ku));
+  const size_t zb = zband_bytes(n, kl, ku) + zrot_bytes(n);
+  int e = spike::launch_zembed(dAB, ldab, n, kl, ku, R, ldr, Dv, stream);
+  if (e) return e;
+  spike_handle h = nullptr;
+  e = spike_factor(2 * n, klr, kur, R, ldr, opts, static_cast<char*>(dWork) + zb, work_bytes - zb, stream, &h);
+  if (e) return e;
+  h->zn = n;
+  h->zd = Dv;
+  *out = h;
+  return 0;
+}
+
+int spike_zsolve(spike_handle h, int32_t nrhs, double* dB, int64_t ldb, int32_t trans, hipStream_t stream) {
+  if (!valid(h) || h->zn < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (nrhs > 0 && h->zn > 0 && dB == nullptr) return -3;
+  if (ldb < (h->zn > 1 ? h->zn : 1)) return -4;
+  if (trans < 0 || trans > 2) return -5;
+  if (nrhs == 0 || h->zn == 0) return 0;
+  // the factors are those of D A (D: the unitary row rotations)
+  const int64_t ld2 = 2 * ldb, zn = h->zn;
+  int e = 0;
+  if (trans == 0) {   // D A z = D f
+    e = spike::launch_zrowscale(dB, ld2, zn, nrhs, h->zd, false, h->kp.status, stream);
+    if (!e) e = solve_common(h, nrhs, dB, ld2, stream, false);
+  } else if (trans == 2) {   // (D A)^H w = f, z = conj(D) w
+    e = solve_common(h, nrhs, dB, ld2, stream, true);
+    if (!e) e = spike::launch_zrowscale(dB, ld2, zn, nrhs, h->zd, true, h->kp.status, stream);
+  } else {   // (D A)^T w = f through (D A)^H conj(w) = conj(f); z = D w
+    e = spike::launch_zconj(dB, ld2, zn, nrhs, h->kp.status, stream);
+    if (!e) e = solve_common(h, nrhs, dB, ld2, stream, true);
+    if (!e) e = spike::launch_zconj(dB, ld2, zn, nrhs, h->kp.status, stream);
+    if (!e) e = spike::launch_zrowscale(dB, ld2, zn, nrhs, h->zd, false, h->kp.status, stream);
+  }
+  return e;
 }
 
 int spike_sweep_counting(int on) {

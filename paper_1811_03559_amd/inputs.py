@@ -107,6 +107,34 @@ def band_paper_dd(n: int, kl: int, ku: int, rng: np.random.Generator, dd: float)
     return ab
 
 
+def zband_dominant(n: int, kl: int, ku: int, rng: np.random.Generator, *, diag_mult=1.05, diag_add=0.0,
+                   diag_mult_range=None) -> np.ndarray:
+    """Complex band: off-diagonal real and imaginary parts iid U[-1, 1]; the
+    diagonal has modulus (off-diagonal row sum of moduli) * mult + add and a
+    phase drawn from U[0, 2 pi).  complex128 array (n, kl + ku + 1) in the
+    real band's layout (ab[j, ku + i - j] = A(i, j))."""
+    ab = rng.uniform(-1.0, 1.0, size=(n, kl + ku + 1)) + 1j * rng.uniform(-1.0, 1.0, size=(n, kl + ku + 1))
+    mask = np.ones((n, kl + ku + 1))
+    _mask_outside(mask, kl, ku)
+    ab *= mask
+    rs = np.zeros(n)
+    for d in range(-ku, kl + 1):            # A(i, i - d) at ab[i - d, ku + d]
+        if d == 0:
+            continue
+        lo, hi = max(0, d), min(n, n + d)
+        if hi > lo:
+            rs[lo:hi] += np.abs(ab[lo - d:hi - d, ku + d])
+    mult = rng.uniform(diag_mult_range[0], diag_mult_range[1], size=n) if diag_mult_range else diag_mult
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    ab[:, ku] = (rs * mult + diag_add) * np.exp(1j * phase)
+    return ab
+
+
+def zrhs(n: int, nrhs: int, rng: np.random.Generator) -> np.ndarray:
+    """Complex right-hand sides, real and imaginary parts N(0, 1): (nrhs, n)."""
+    return rng.standard_normal(size=(nrhs, n)) + 1j * rng.standard_normal(size=(nrhs, n))
+
+
 def rhs(n: int, nrhs: int, rng: np.random.Generator) -> np.ndarray:
     """X_true (or a right-hand side) ~ N(0, 1), shape (nrhs, n)."""
     return rng.standard_normal(size=(nrhs, n))

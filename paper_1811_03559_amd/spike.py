@@ -161,6 +161,13 @@ def lib():
             L.spike_autotune.restype = ctypes.c_int
             L.spike_autotune.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, _c_i32, ctypes.POINTER(Opts),
                                          _c_p, _c_size, _c_p, _c_i64, _c_p, ctypes.POINTER(TuneResult)]
+            L.spike_zworkspace_size.restype = ctypes.c_int
+            L.spike_zworkspace_size.argtypes = [_c_i64, _c_i32, _c_i32, ctypes.POINTER(Opts), ctypes.POINTER(_c_size)]
+            L.spike_zfactor.restype = ctypes.c_int
+            L.spike_zfactor.argtypes = [_c_i64, _c_i32, _c_i32, _c_p, _c_i64, ctypes.POINTER(Opts), _c_p, _c_size,
+                                        _c_p, ctypes.POINTER(_c_p)]
+            L.spike_zsolve.restype = ctypes.c_int
+            L.spike_zsolve.argtypes = [_c_p, _c_i32, _c_p, _c_i64, _c_i32, _c_p]
             L.spike_krylov_default_opts.restype = None
             L.spike_krylov_default_opts.argtypes = [ctypes.POINTER(KrylovOpts)]
             L.spike_krylov_workspace_size.restype = ctypes.c_int
@@ -433,6 +440,64 @@ class sweep_counting:
     def __exit__(self, *exc):
         lib().spike_sweep_counting(0)
         return False
+
+
+class ZFactorization(Factorization):
+    """A complex band's SPIKE factorisation (spike_zfactor: the real
+    embedding with 2 x 2 blocks [[Re a, -Im a], [Im a, Re a]], factored on
+    the real path).  ``ab``: complex128 CUDA tensor (n, ldab), the real
+    band's layout; options as Factorization, for the 2n-row embedding."""
+
+    _TRANS = {"N": 0, "T": 1, "C": 2, False: 0, True: 1}
+
+    def __init__(self, ab, kl, ku, *, stream=None, workspace=None, **opts):
+        import torch
+        if not isinstance(ab, torch.Tensor) or ab.dtype != torch.complex128 or not ab.is_cuda \
+                or ab.dim() != 2 or not ab.is_contiguous():
+            raise ValueError("band must be a contiguous 2-D complex128 CUDA tensor (n, ldab)")
+        if int(ab.shape[1]) < int(kl) + int(ku) + 1:
+            raise ValueError("band has ldab < kl + ku + 1")
+        self.n, self.ldab = int(ab.shape[0]), int(ab.shape[1])
+        self.kl, self.ku = int(kl), int(ku)
+        self.opts = make_opts(**opts)
+        self.nrhs_max = self.opts.nrhs_max
+        need = _c_size()
+        rc = lib().spike_zworkspace_size(self.n, self.kl, self.ku, ctypes.byref(self.opts), ctypes.byref(need))
+        if rc != 0:
+            raise SpikeError("spike_zworkspace_size", rc)
+        if workspace is None:
+            workspace = torch.empty(max(need.value, 256), dtype=torch.uint8, device=ab.device)
+        if workspace.numel() < need.value:
+            raise ValueError("workspace too small")
+        self.ab, self.ws, self.device = ab, workspace, ab.device
+        h = ctypes.c_void_p()
+        rc = lib().spike_zfactor(self.n, self.kl, self.ku, ctypes.c_void_p(ab.data_ptr()), self.ldab,
+                                 ctypes.byref(self.opts), ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel(), _stream_handle(stream), ctypes.byref(h))
+        if rc != 0:
+            raise SpikeError("spike_zfactor", rc)
+        self.h = h
+
+    def solve_(self, B, *, trans="N", stream=None):
+        """In-place solve of op(A) Z = B, B a complex128 CUDA tensor (nrhs, n)
+        or (n,) with unit column stride; trans "N", "T" (A^T) or "C" (A^H)."""
+        import torch
+        if not isinstance(B, torch.Tensor) or B.dtype != torch.complex128 or not B.is_cuda:
+            raise ValueError("B must be a complex128 CUDA tensor")
+        if B.dim() == 1:
+            B = B.view(1, -1)
+        if B.dim() != 2 or B.shape[1] != self.n or (self.n > 1 and B.stride(1) != 1) \
+                or (B.shape[0] > 1 and B.stride(0) < max(self.n, 1)):
+            raise ValueError("B must have shape (nrhs, n) with unit column stride")
+        ldb = B.stride(0) if B.shape[0] > 1 else max(self.n, 1)
+        rc = lib().spike_zsolve(self.h, int(B.shape[0]), ctypes.c_void_p(B.data_ptr()), int(ldb),
+                                self._TRANS[trans], _stream_handle(stream))
+        if rc != 0:
+            raise SpikeError("spike_zsolve", rc)
+        return B
+
+    def solve_gmres_(self, *a, **kw):
+        raise NotImplementedError("GMRES runs on real systems")
 
 
 def levels_for(p: int) -> int:

@@ -119,12 +119,13 @@ def test_degenerate_sizes():
 def usmani_inverse(m, b, a, c):
     """Inverse of the Toeplitz tridiagonal tridiag(b, a, c) of order m (b on the
     sub-diagonal, c on the super-diagonal), Usmani (1994)."""
-    theta = np.zeros(m + 2)
+    dt = np.result_type(a, b, c, float)    # complex entries give a complex inverse
+    theta = np.zeros(m + 2, dtype=dt)
     theta[0], theta_m1 = 1.0, 0.0          # theta_0 = 1, theta_{-1} = 0
     theta[1] = a * theta[0] - b * c * theta_m1
     for i in range(2, m + 1):
         theta[i] = a * theta[i - 1] - b * c * theta[i - 2]
-    phi = np.zeros(m + 3)                  # phi_{m+1} = 1, phi_{m+2} = 0
+    phi = np.zeros(m + 3, dtype=dt)        # phi_{m+1} = 1, phi_{m+2} = 0
     phi[m + 1], phi[m + 2] = 1.0, 0.0
     for i in range(m, 0, -1):
         phi[i] = a * phi[i + 1] - b * c * phi[i + 2]
@@ -132,7 +133,7 @@ def usmani_inverse(m, b, a, c):
     def th(i):
         return theta_m1 if i == -1 else theta[i]
 
-    T = np.zeros((m, m))
+    T = np.zeros((m, m), dtype=dt)
     for i in range(1, m + 1):
         for j in range(1, m + 1):
             if i <= j:
@@ -394,3 +395,69 @@ def test_gbtrf_then_gbtrs_is_gbsv(kl, ku, pivot, trans):
     A = dense_from_band(ab, kl, ku)
     ref = np.linalg.solve(A.T if trans else A, F.T).T
     assert oracle.fwd_err(X, ref) <= 1e-14 * np.linalg.cond(A, 1) * n
+
+
+# ---------------------------------------------------------------- complex bands
+
+def zdense_from_band(ab, kl, ku):
+    n = ab.shape[0]
+    A = np.zeros((n, n), dtype=complex)
+    for j in range(n):
+        for i in range(max(0, j - ku), min(n, j + kl + 1)):
+            A[i, j] = ab[j, ku + i - j]
+    return A
+
+
+def zrand_band(n, kl, ku, seed, dominant):
+    rng = inputs.rng_for(seed)
+    if dominant:
+        return inputs.zband_dominant(n, kl, ku, rng, diag_mult=1.0, diag_add=1.0)
+    return inputs.zband_dominant(n, kl, ku, rng, diag_mult=0.0, diag_add=0.3)   # no dominance
+
+
+@pytest.mark.parametrize("kl,ku", [(0, 0), (1, 2), (3, 1), (4, 4)])
+@pytest.mark.parametrize("pivot", [False, True])
+@pytest.mark.parametrize("trans", ["N", "T", "C"])
+def test_zgbsv_matches_dense_complex_solve(kl, ku, pivot, trans):
+    n = 41
+    ab = zrand_band(n, kl, ku, 300 + 10 * kl + ku, dominant=not pivot)
+    A = zdense_from_band(ab, kl, ku)
+    op = {"N": A, "T": A.T, "C": A.conj().T}[trans]
+    F = inputs.zrhs(n, 2, inputs.rng_for(13))
+    X = oracle.zgbsv(ab, kl, ku, F, pivot=pivot, trans=trans)
+    ref = np.linalg.solve(op, F.T).T
+    kappa = np.linalg.cond(A, 1)
+    assert oracle.fwd_err(X, ref) <= 1e-14 * kappa * n
+    np.testing.assert_allclose(oracle.zgbmv(ab, kl, ku, X, trans=trans), F, atol=1e-10 * np.abs(F).max())
+    assert oracle.zrelres(ab, kl, ku, X, F, trans=trans) <= 1e-14
+
+
+@pytest.mark.parametrize("trans", ["N", "T", "C"])
+def test_zgbmv_and_zrelres_against_dense(trans):
+    n, kl, ku = 37, 3, 2
+    ab = zrand_band(n, kl, ku, 77, dominant=True)
+    A = zdense_from_band(ab, kl, ku)
+    op = {"N": A, "T": A.T, "C": A.conj().T}[trans]
+    X = inputs.zrhs(n, 3, inputs.rng_for(78))
+    np.testing.assert_allclose(oracle.zgbmv(ab, kl, ku, X, trans=trans), (op @ X.T).T, rtol=1e-13, atol=1e-13)
+    F = (op @ X.T).T + 1e-3 * inputs.zrhs(n, 3, inputs.rng_for(79))
+    r = F - (op @ X.T).T
+    rel = max(np.abs(r[c]).max() / (np.abs(op).sum(axis=1).max() * np.abs(X[c]).max()) for c in range(3))
+    assert abs(oracle.zrelres(ab, kl, ku, X, F, trans=trans) - rel) <= 1e-12 * rel
+
+
+@pytest.mark.parametrize("trans", ["N", "T", "C"])
+def test_zgbsv_complex_toeplitz_closed_form(trans):
+    """Usmani's inverse holds over the complex numbers: tridiag(b, a, c) with
+    complex entries, the oracle's solution against it."""
+    m = 30
+    b, a, c = 0.7 - 0.4j, 3.0 + 1.5j, -0.5 + 0.9j
+    Tinv = usmani_inverse(m, b, a, c)
+    ab = np.zeros((m, 3), dtype=complex)
+    ab[:, 0], ab[:, 1], ab[:, 2] = c, a, b        # ku = kl = 1: A(j-1, j) = c, A(j+1, j) = b
+    ab[0, 0] = 0
+    ab[-1, 2] = 0
+    F = inputs.zrhs(m, 2, inputs.rng_for(80))
+    op_inv = {"N": Tinv, "T": Tinv.T, "C": Tinv.conj().T}[trans]
+    X = oracle.zgbsv(ab, 1, 1, F, pivot=False, trans=trans)
+    np.testing.assert_allclose(X, (op_inv @ F.T).T, rtol=1e-12, atol=1e-12)
