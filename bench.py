@@ -343,6 +343,68 @@ def bench_p_sweep(dab, ab, k, F, ps=(250, 500)):
     return out
 
 
+def bench_ratio_grid(dab, ab, k, p=192, nrhss=(80, 160, 320), r12s=(0.5, 0.75, 1.0, 1.25, 1.5),
+                     r13s=(1.0, 1.5, 2.0, 2.5, 3.0)):
+    """The partition-ratio experiment on the GPU: factor and solve times of
+    the headline band over an (R12, R13) grid of partition sizes, with the
+    paper's thread layout at p = 192 = 128 + 64 (64 two-thread partitions
+    split in two leaves, 62 single-thread inner partitions, first and last),
+    for nrhs = 80, 160 and 320 (nrhs / k = 1/2, 1, 2).  K is measured as the
+    paper prescribes (solve time over factor time at nrhs = k, equal
+    sizes) and the model's compromise ratios R13 (eq. R13_calculation) and
+    R12 = R13 / 2 are timed beside the grid."""
+    import torch
+    from paper_1811_03559_amd import spike
+    n = ab.shape[0]
+    nmax = max(nrhss)
+    Fbig = torch.randn((nmax, n), dtype=torch.float64, device=dab.device,
+                       generator=torch.Generator(device=dab.device).manual_seed(1811))
+    base = dict(p=p, tree="paper", nrhs_max=nmax)
+
+    def measure(opts):
+        holder = {}
+
+        def fac():
+            holder["f"] = spike.Factorization(dab, k, k, **opts)
+        t_f = _timed(fac)
+        f = holder["f"]
+        res = {"factor_ms": t_f}
+        for r in nrhss:
+            B = Fbig[:r].clone()
+            res["solve_ms_nrhs%d" % r] = _timed(lambda: f.solve_(B))
+        f.close()
+        return res
+
+    eq = measure(dict(base, sizing="equal"))
+    K = eq["solve_ms_nrhs%d" % k] / eq["factor_ms"] if ("solve_ms_nrhs%d" % k) in eq else None
+    grid = []
+    for r12 in r12s:
+        for r13 in r13s:
+            try:
+                m = measure(dict(base, sizing="ratios", r12=r12, r13=r13))
+            except spike.SpikeError as e:
+                m = {"error": e.code}
+            m.update({"r12": r12, "r13": r13})
+            grid.append(m)
+    model = {}
+    if K:
+        for r in nrhss:
+            R13 = (1.0 + 1.5 * K + 2.0 * K * r / k) / (1.0 + K * r / k)
+            m = measure(dict(base, sizing="ratios", r12=R13 / 2, r13=R13))
+            model["nrhs%d" % r] = {"r12": R13 / 2, "r13": R13, "factor_ms": m["factor_ms"],
+                                   "solve_ms": m["solve_ms_nrhs%d" % r]}
+    best = {}
+    for r in nrhss:
+        ok = [g for g in grid if "error" not in g]
+        for what, key in (("factor", lambda g: g["factor_ms"]),
+                          ("solve", lambda g: g["solve_ms_nrhs%d" % r]),
+                          ("combined", lambda g: g["factor_ms"] + g["solve_ms_nrhs%d" % r])):
+            g = min(ok, key=key)
+            best["nrhs%d_%s" % (r, what)] = {"r12": g["r12"], "r13": g["r13"], "ms": key(g)}
+    return {"p": p, "tree": "paper", "K": K, "equal_sizes": eq, "grid": grid, "model_ratios": model,
+            "best": best}
+
+
 def bench_pivoting(n=500_000, k=64, nrhs=16, ps=(2, 3, 256)):
     """Pivoting SPIKE next to non-pivoting SPIKE (with boosting) on the
     ill-conditioned N(0,1) row-scaled band: errors against the manufactured
@@ -558,8 +620,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-detail", action="store_true",
                     help="skip every detail section (phase times and the other workloads)")
-    ap.add_argument("--sections", default="psweep,pivoting,mixed,complex,serving",
-                    help="detail sections: psweep, pivoting, mixed, complex, serving")
+    ap.add_argument("--sections", default="psweep,ratios,pivoting,mixed,complex,serving",
+                    help="detail sections: psweep, ratios, pivoting, mixed, complex, serving")
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
@@ -678,7 +740,12 @@ def main():
         if "psweep" in secs:
             note("p sweep")
             detail["p_sweep"] = bench_p_sweep(dab, ab, k, F)
-        del dab, dF, dF64, ws
+        del dF64, ws
+        torch.cuda.empty_cache()
+        if "ratios" in secs:
+            note("partition ratio grid")
+            detail["ratio_grid"] = bench_ratio_grid(dab, ab, k)
+        del dab, dF
         torch.cuda.empty_cache()
         if "pivoting" in secs:
             note("pivoting")

@@ -65,9 +65,17 @@ typedef struct spike_opts {
     int32_t precision;  /* 0 = FP64 throughout; 1 = FP32 block factors and
                            sweeps, FP64 reduced system, FP64 residual and
                            iterative refinement                           [0]    */
-    int32_t sizing;     /* 0 = equal partitions; 1 = first/last partitions
-                           enlarged by the ratio R13 of the paper's
-                           load-balancing section                        [0]    */
+    int32_t sizing;     /* 0 = equal partitions; 1 = sizes from the paper's
+                           load-balancing ratios computed from K and
+                           nrhs_hint (R13, eq. R13_calculation, and
+                           R12 = R13 / 2); 2 = sizes from the explicit
+                           ratios r12 and r13 below.  First and last
+                           partitions get n1, two-thread partitions of the
+                           paper layout (tree 1) n2, split in two leaves,
+                           single-thread inner partitions n3, with
+                           n1 = n R12 R13 / (2 R12 R13 + x R13 + y R12),
+                           n2 = n1 / R12, n3 = n1 / R13 (x two-thread, y
+                           single-thread inner partitions)                [0]    */
     double K;           /* solve/factor cost constant K = K2/K1 used by
                            R13 sizing; <= 0 selects 1.0                   [0]    */
     int32_t nrhs_hint;  /* expected nrhs for R13 sizing; 0 = unknown       [0]    */
@@ -102,6 +110,8 @@ typedef struct spike_opts {
                            then runs over the 2^m nodes.  Any other p is
                            an error (-4); with p = 0 the planner's count
                            is lowered to the nearest admissible one.  [0] */
+    double r12;         /* sizing 2: n1 / n2 (> 0)                        [0]    */
+    double r13;         /* sizing 2: n1 / n3 (> 0)                        [0]    */
 } spike_opts;
 
 /* Device-side status, read by spike_info() (blocking copy). */

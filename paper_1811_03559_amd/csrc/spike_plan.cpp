@@ -1,10 +1,12 @@
 // Host planner for the recursive SPIKE solver.
 //
 // Partition sizing follows the load-balancing section of the paper: equal
-// sizes, or first/last partitions enlarged by R13 = n1/n3 (eq.
-// R13_calculation) with every inner partition single-threaded (x = 0
-// two-thread partitions, y = p - 2), so n1 = n R13 / (2 R13 + p - 2) and
-// n3 = n / (2 R13 + p - 2).
+// sizes, or three sizes n1 (first/last), n2 (two-thread inner partitions of
+// the paper layout, as two leaves of n2 / 2) and n3 (single-thread inner)
+// from R12 = n1/n2 and R13 = n1/n3: eq. R13_calculation with R12 = R13/2
+// (eq. R12_calculation), or given explicitly.  With the balanced tree every
+// inner partition is single-threaded (x = 0, y = p - 2), so
+// n1 = n R13 / (2 R13 + p - 2) and n3 = n / (2 R13 + p - 2).
 //
 // The reduced system is solved over a merge tree.  The balanced tree works
 // for any p: at every level adjacent nodes are paired left to right and an
@@ -22,6 +24,9 @@
 // With R13 sizing the two layouts give the same sizes: the paper's R12 =
 // R13/2 makes each half of a two-thread partition n2/2 = n3 rows long, and
 // 2 r + (2^m - 2 - r) = p - 2 inner leaves of n3 rows remain either way.
+// Explicit ratios with R12 != R13/2 size the two-thread halves apart from
+// the single-thread partitions, which is the (R12, R13) plane the paper's
+// ratio experiments scan.
 #include "spike_plan.hpp"
 
 #include <algorithm>
@@ -43,6 +48,8 @@ void default_opts(spike_opts *o) {
   o->max_refine = -1;
   o->refine_tol = 1e-13;
   o->tree = 0;
+  o->r12 = 0.0;
+  o->r13 = 0.0;
 }
 
 // Paper tree layout: is p = 2^m + r with 0 <= r <= 2^m - 2?  Sets m2 = 2^m.
@@ -76,8 +83,8 @@ static int choose_p(int64_t n, int kl, int ku) {
 
 int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl, bool narrow_pivot_panels) {
   if (o.p < 0 || (o.pivot != 0 && o.pivot != 1) || (o.precision != 0 && o.precision != 1) ||
-      (o.sizing != 0 && o.sizing != 1) || (o.tree != 0 && o.tree != 1) || o.nrhs_max < 0 ||
-      o.nrhs_hint < 0)
+      (o.sizing < 0 || o.sizing > 2) || (o.tree != 0 && o.tree != 1) || o.nrhs_max < 0 ||
+      o.nrhs_hint < 0 || (o.sizing == 2 && !(o.r12 > 0.0 && o.r13 > 0.0)))
     return -4;
   pl = Plan();
   pl.n = n;
@@ -111,15 +118,31 @@ int make_plan(int64_t n, int kl, int ku, const spike_opts &o, Plan &pl, bool nar
   std::vector<int64_t> sz(p, 0);
   if (p == 1) {
     sz[0] = n;
-  } else if (o.sizing == 1 && p >= 3) {
-    double r = pl.nrhs_hint > 0 ? (double)pl.nrhs_hint / std::max(1, pl.kmax) : 0.0;
-    double R13 = ratio_r13(pl.K, r);
-    double denom = 2.0 * R13 + (p - 2);
-    int64_t n1 = (int64_t)std::floor((double)n * R13 / denom);
-    int64_t n3 = (int64_t)std::floor((double)n / denom);
+  } else if (o.sizing != 0 && p >= 3) {
+    // R12 / R13 sizing.  With the paper layout the leaves 1 .. 2x are the
+    // halves of x two-thread partitions (n2 / 2 rows each), the next y
+    // leaves single-thread inner partitions (n3); the balanced tree has
+    // x = 0.
+    double R12, R13;
+    if (o.sizing == 2) {
+      R12 = o.r12;
+      R13 = o.r13;
+    } else {
+      double r = pl.nrhs_hint > 0 ? (double)pl.nrhs_hint / std::max(1, pl.kmax) : 0.0;
+      R13 = ratio_r13(pl.K, r);
+      R12 = 0.5 * R13;
+    }
+    const int x = (o.tree == 1) ? p - m2 : 0;
+    const int y = p - 2 - 2 * x;
+    const double denom = 2.0 * R12 * R13 + x * R13 + y * R12;
+    const int64_t n1 = (int64_t)std::floor((double)n * R12 * R13 / denom);
+    const int64_t n2h = (int64_t)std::floor(0.5 * (double)n * R13 / denom);
+    const int64_t n3 = (int64_t)std::floor((double)n * R12 / denom);
     sz[0] = sz[p - 1] = n1;
-    for (int i = 1; i < p - 1; ++i) sz[i] = n3;
-    int64_t rem = n - 2 * n1 - (int64_t)(p - 2) * n3;
+    for (int i = 1; i <= 2 * x; ++i) sz[i] = n2h;
+    for (int i = 2 * x + 1; i < p - 1; ++i) sz[i] = n3;
+    int64_t rem = n;
+    for (int i = 0; i < p; ++i) rem -= sz[i];
     for (int i = 1; rem > 0; i = (i % (p - 2)) + 1, --rem) sz[i] += 1;
   } else {
     int64_t base = n / p, rem = n % p;

@@ -32,7 +32,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("p", _c_i32), ("pivot", _c_i32), ("precision", _c_i32), ("sizing", _c_i32),
                 ("K", _c_dbl), ("nrhs_hint", _c_i32), ("nrhs_max", _c_i32),
                 ("boost_tau", _c_dbl), ("max_refine", _c_i32), ("refine_tol", _c_dbl),
-                ("tree", _c_i32)]
+                ("tree", _c_i32), ("r12", _c_dbl), ("r13", _c_dbl)]
 
 
 class Status(ctypes.Structure):
@@ -220,16 +220,17 @@ def profile_report():
 
 def make_opts(p=0, pivot=False, precision="fp64", sizing="equal", K=0.0, nrhs_hint=0,
               nrhs_max=64, boost_tau=-1.0, max_refine=-1, refine_tol=1e-13,
-              tree="balanced") -> Opts:
+              tree="balanced", r12=0.0, r13=0.0) -> Opts:
     """spike_opts from keyword options (the header documents each field):
-    precision "fp64" | "mixed", sizing "equal" | "r13", tree "balanced" |
-    "paper" (the 2^m + r layout, which rejects other p)."""
+    precision "fp64" | "mixed", sizing "equal" | "r13" (ratios from K and
+    nrhs_hint) | "ratios" (the explicit r12 = n1/n2 and r13 = n1/n3), tree
+    "balanced" | "paper" (the 2^m + r layout, which rejects other p)."""
     o = Opts()
     lib().spike_default_opts(ctypes.byref(o))
     o.p = int(p)
     o.pivot = 1 if pivot else 0
     o.precision = {"fp64": 0, "mixed": 1, 0: 0, 1: 1}[precision]
-    o.sizing = {"equal": 0, "r13": 1, 0: 0, 1: 1}[sizing]
+    o.sizing = {"equal": 0, "r13": 1, "ratios": 2, 0: 0, 1: 1, 2: 2}[sizing]
     o.K = float(K)
     o.nrhs_hint = int(nrhs_hint)
     o.nrhs_max = int(nrhs_max)
@@ -237,6 +238,8 @@ def make_opts(p=0, pivot=False, precision="fp64", sizing="equal", K=0.0, nrhs_hi
     o.max_refine = int(max_refine)
     o.refine_tol = float(refine_tol)
     o.tree = {"balanced": 0, "paper": 1, 0: 0, 1: 1}[tree]
+    o.r12 = float(r12)
+    o.r13 = float(r13)
     return o
 
 
@@ -593,7 +596,8 @@ def autotune(ab, kl, ku, nrhs=1, stream=None, **base):
         raise SpikeError("spike_autotune", rc)
     r = res.opts
     opts = {"p": r.p, "pivot": bool(r.pivot), "precision": "mixed" if r.precision else "fp64",
-            "sizing": "r13" if r.sizing else "equal", "K": r.K, "nrhs_hint": r.nrhs_hint,
+            "sizing": ("equal", "r13", "ratios")[r.sizing], "r12": r.r12, "r13": r.r13,
+            "K": r.K, "nrhs_hint": r.nrhs_hint,
             "nrhs_max": r.nrhs_max, "tree": "paper" if r.tree else "balanced"}
     return opts, {"factor_ms": res.factor_ms, "solve_ms": res.solve_ms, "K": res.K,
                   "candidates": res.candidates}

@@ -170,8 +170,9 @@ int main(int argc, char** argv) {
   if (argc != 3) return 2;
   FILE* f = std::fopen(argv[1], "rb");
   if (!f) return 2;
-  int64_t hdr[7];
-  if (std::fread(hdr, 8, 7, f) != 7) return 2;
+  int64_t hdr[9];
+  double ratios[2];
+  if (std::fread(hdr, 8, 9, f) != 9 || std::fread(ratios, 8, 2, f) != 2) return 2;
   const int64_t n = hdr[0];
   const int kl = (int)hdr[1], ku = (int)hdr[2], p = (int)hdr[3], pivot = (int)hdr[4], nrhs = (int)hdr[5];
   const bool trans = hdr[6] != 0;
@@ -186,6 +187,10 @@ int main(int argc, char** argv) {
   o.p = p;
   o.pivot = pivot;
   o.nrhs_max = std::max(1, nrhs);
+  o.tree = (int)hdr[7];
+  o.sizing = (int)hdr[8];
+  o.r12 = ratios[0];
+  o.r13 = ratios[1];
   Plan pl;
   if (make_plan(n, kl, ku, o, pl, /*narrow_pivot_panels=*/true)) return 3;
   Regions R = carve(pl);

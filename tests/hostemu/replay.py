@@ -56,9 +56,10 @@ def build(workdir: str | None = None) -> str:
 
 
 def run(exe: str, ab: np.ndarray, kl: int, ku: int, F: np.ndarray, p: int, pivot: bool, trans: bool,
-        timeout: float = 600.0, sweeps: bool = False):
+        timeout: float = 600.0, sweeps: bool = False, tree: str = "balanced", ratios=None):
     """Factor and solve on the CPU replay.  ab: (n, kl+ku+1) band rows in the
-    binding's layout; F: (nrhs, n).  Returns (info, X with F's shape), or
+    binding's layout; F: (nrhs, n); tree "balanced" | "paper"; ratios None
+    (equal sizes) or (R12, R13).  Returns (info, X with F's shape), or
     (info, X, sweep counters) with sweeps=True."""
     n = ab.shape[0]
     F = np.atleast_2d(F)
@@ -66,7 +67,9 @@ def run(exe: str, ab: np.ndarray, kl: int, ku: int, F: np.ndarray, p: int, pivot
     work = tempfile.mkdtemp(prefix="spike_hostemu_run_")
     fin, fout = os.path.join(work, "in.bin"), os.path.join(work, "out.bin")
     with open(fin, "wb") as f:
-        np.array([n, kl, ku, p, int(pivot), nrhs, int(trans)], dtype=np.int64).tofile(f)
+        np.array([n, kl, ku, p, int(pivot), nrhs, int(trans), {"balanced": 0, "paper": 1}[tree],
+                  0 if ratios is None else 2], dtype=np.int64).tofile(f)
+        np.array(ratios if ratios is not None else (0.0, 0.0), dtype=np.float64).tofile(f)
         np.ascontiguousarray(ab, dtype=np.float64).tofile(f)
         np.ascontiguousarray(F, dtype=np.float64).tofile(f)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0:halt_on_error=1",

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from gpu_util import check, run
-from paper_1811_03559_amd import inputs
+from paper_1811_03559_amd import inputs, spike
 
 pytestmark = pytest.mark.gpu
 
@@ -55,6 +55,55 @@ def test_paper_tree_mixed_precision(trans):
     assert 1 <= info["refine_iters"] <= 6, info
     assert 0 <= info["berr"] <= 1e-13, info
     check(ab, k, k, F, X, trans=trans, pivot=False, X_true=X_true)
+
+
+@pytest.mark.parametrize("p", [11, 21])
+@pytest.mark.parametrize("r12,r13", [(1.2, 2.0), (0.8, 3.0)])
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("k", [4, 40])
+def test_paper_tree_ratio_sizing(p, r12, r13, trans, k):
+    """The paper layout with explicit (R12, R13) partition sizes, R12 off the
+    R13 / 2 line so the halves of the two-thread partitions (which merge
+    first, also in the transpose solve) differ in size from the
+    single-thread partitions."""
+    n = p * (3 * k + 90) + 7
+    ab = dd_band(n, k, k, 9300 + p + k, mult=1.05, add=0.0)
+    F = inputs.rhs(n, 2, inputs.rng_for(9400 + p))
+    opts = dict(p=p, tree="paper", sizing="ratios", r12=r12, r13=r13)
+    X, info, plan = run(ab, k, k, F, trans=trans, **opts)
+    assert info["info"] == 0 and plan["p"] == p
+    sz = spike.plan_query(n, k, k, **opts)["sizes"]
+    assert abs(sz[1] - sz[-2]) > 2
+    check(ab, k, k, F, X, trans=trans, pivot=False)
+
+
+@pytest.mark.parametrize("k", [8, 40])
+def test_paper_tree_sweep_counts(k):
+    """Table tab:sweeps for the paper layout: the halves of a two-thread
+    partition (leaves 1 .. 2r) each run the middle partition's 3 factor and
+    4 solve sweeps, so together they do the table's 3 and 4 sweeps over
+    the two-thread partition's rows, as the SPIKE 2x2 kernel does; the
+    transpose solve too."""
+    import torch
+    import sweep_table
+    from paper_1811_03559_amd import spike
+    p = 11                                   # 2^3 + 3: leaves 1..6 two-thread halves
+    n = p * (5 * k + 90) + 5
+    ab = dd_band(n, k, k, 9500 + k, mult=1.05, add=0.0)
+    F = inputs.rhs(n, 2, inputs.rng_for(9501))
+    dab = torch.from_numpy(ab).cuda()
+    with spike.sweep_counting():
+        fac = spike.Factorization(dab, k, k, p=p, tree="paper", sizing="ratios", r12=1.2, r13=2.0)
+    B = torch.from_numpy(F.copy()).cuda()
+    Bt = torch.from_numpy(F.copy()).cuda()
+    fac.solve_(B)
+    fac.solve_(Bt, trans=True)
+    torch.cuda.synchronize()
+    counts = fac.sweep_counts()
+    fac.close()
+    sweep_table.check(counts, p)
+    check(ab, k, k, F, B.cpu().numpy(), pivot=False)
+    check(ab, k, k, F, Bt.cpu().numpy(), trans=True, pivot=False)
 
 
 def test_batch_mixing_trees_equals_individual_solves_bitwise():

@@ -120,6 +120,54 @@ def test_r13_sizing_matches_closed_form(nrhs, K):
     assert sz[0] / sz[1] == pytest.approx(R13, rel=1e-3)
 
 
+@pytest.mark.parametrize("p,tree,x", [(11, "paper", 3), (21, "paper", 5), (16, "paper", 0),
+                                       (11, "balanced", 0), (24, "balanced", 0)])
+@pytest.mark.parametrize("r12,r13", [(1.2, 2.0), (1.0, 2.0), (1.5, 1.0), (0.6, 3.0)])
+def test_explicit_ratio_sizing_matches_closed_form(p, tree, x, r12, r13):
+    """Sizing from explicit R12 = n1/n2 and R13 = n1/n3 (the load-balancing
+    section's partition-size equations): x two-thread partitions (the paper
+    layout's r = p - 2^m, each split in two leaves of n2 / 2), y = p - 2 - 2x
+    single-thread inner partitions."""
+    n, k = 1_000_003, 40
+    sz = spike.plan_query(n, k, k, p=p, sizing="ratios", r12=r12, r13=r13, tree=tree)["sizes"]
+    y = p - 2 - 2 * x
+    den = 2 * r12 * r13 + x * r13 + y * r12
+    n1, n2, n3 = n * r12 * r13 / den, n * r13 / den, n * r12 / den
+    assert len(sz) == p and sum(sz) == n
+    assert 2 * n1 + x * n2 + y * n3 == pytest.approx(n, rel=1e-12)
+    assert sz[0] == sz[-1] == math.floor(n1)
+    for i in range(1, 2 * x + 1):
+        assert abs(sz[i] - n2 / 2) <= 3, (i, sz[i], n2 / 2)
+    for i in range(2 * x + 1, p - 1):
+        assert abs(sz[i] - n3) <= 3, (i, sz[i], n3)
+    assert sz[0] / sz[-2 if y else 1] == pytest.approx(r13 if y else 2 * r12, rel=1e-4)
+    if x:
+        assert (sz[1] + sz[2]) == pytest.approx(n1 / r12, abs=6)
+
+
+def test_ratio_sizing_with_half_r13_equals_model_sizing():
+    """R12 = R13 / 2 (the paper's choice n2 = 2 n3) given explicitly sizes
+    the partitions as the model sizing does with the same R13, for both
+    layouts."""
+    n, k, p, K, nrhs = 1_000_000, 160, 12, 4.0 / 3.0, 80
+    R13 = oracle.r13(K, nrhs / k)
+    for tree in ("balanced", "paper"):
+        a = spike.plan_query(n, k, k, p=p, sizing="r13", K=K, nrhs_hint=nrhs, tree=tree)["sizes"]
+        b = spike.plan_query(n, k, k, p=p, sizing="ratios", r12=R13 / 2, r13=R13, tree=tree)["sizes"]
+        assert max(abs(u - v) for u, v in zip(a, b)) <= 1, tree
+
+
+def test_ratio_sizing_rejects_nonpositive_ratios():
+    for r12, r13 in ((0.0, 2.0), (1.0, 0.0), (-1.0, 2.0), (float("nan"), 2.0)):
+        with pytest.raises(spike.SpikeError) as e:
+            spike.plan_query(100_000, 4, 4, p=6, sizing="ratios", r12=r12, r13=r13)
+        assert e.value.code == -4
+    # ratios so skewed that a partition falls below kl + ku rows
+    with pytest.raises(spike.SpikeError) as e:
+        spike.plan_query(10_000, 40, 40, p=6, sizing="ratios", r12=1.0, r13=1000.0)
+    assert e.value.code == -4
+
+
 def test_argument_errors():
     with pytest.raises(spike.SpikeError) as e:
         spike.plan_query(-1, 2, 2)

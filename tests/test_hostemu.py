@@ -106,3 +106,23 @@ def test_sweep_table_is_the_papers():
     the counter test above compare against the wrong numbers)."""
     import sweep_table
     assert sweep_table.table() == {"first_last": (0, 2), "middle": (3, 4)}
+
+
+@pytest.mark.parametrize("pivot", [False, True])
+@pytest.mark.parametrize("trans", [False, True])
+def test_paper_tree_ratio_sizing(exe, pivot, trans):
+    """The paper layout (p = 2^m + r: 11 = 8 + 3, leaves 1..6 the halves of
+    the two-thread partitions, merged first) with explicit (R12, R13) sizes
+    off the R12 = R13 / 2 line, on the workgroup kernels: the transposed
+    level-1 merge included, and the sweep counters give the table's counts
+    for every leaf."""
+    import sweep_table
+    n, k, p = 11 * 260 + 7, 12, 11
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(9600 + k), diag_mult=1.05, diag_add=0.0)
+    F = inputs.rhs(n, 2, inputs.rng_for(9601))
+    info, X, sw = replay.run(exe, ab, k, k, F, p=p, pivot=pivot, trans=trans, sweeps=True, tree="paper",
+                             ratios=(1.2, 2.0))
+    assert info == 0
+    _check(ab, k, k, F, X, trans)
+    sweep_table.check(sweep_table.from_array(sw), p,
+                      stages=("factor", "solve_t" if trans else "solve"))
