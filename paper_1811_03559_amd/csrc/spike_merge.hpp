@@ -589,6 +589,374 @@ __global__ __launch_bounds__(NWR * 64) void k_mlu_reg(KParams k, int mbeg) {
   diag_inverses<double>(MluDiagAcc{s_dg, n}, k.sdinv + (int64_t)mi * nbs * dinv_stride(), tid, NWR * 64);
 }
 
+// Blocked variant for order n <= 16 NBT: the same pivot rule as k_mlu_reg
+// (the pivot of step j is the largest |entry| of column j among the rows not
+// yet chosen, ties to the smallest row index; no rows move, and the row
+// chosen at step i becomes row i of P S), with the rank-1 updates gathered
+// into rank-16 products on the matrix cores.  Wavefront w < nb (nb = the
+// number of 16-column blocks) holds column block w of S as 16 x 16 MFMA
+// tiles; one more wavefront factors the blocks, one at a time, with one row
+// per lane and slot in registers (no workgroup barrier inside a block).  For
+// block J it publishes the multipliers of every row, masked so that rows
+// chosen in earlier blocks get none and the row chosen at step t of the
+// block keeps only those of steps < t, and the inverse of the unit lower
+// triangle L11 of the block's pivot rows.  Every wavefront right of the
+// block then forms U12 = L11^{-1} (its pivot rows) and subtracts
+// (multipliers) x U12 from all its tiles, which leaves U12 in the pivot rows
+// and the Schur complement elsewhere; tiles whose rows were all chosen in
+// earlier blocks are skipped.  The owner of block J + 1 updates first and
+// hands it to the factoring wavefront through LDS; the others update while
+// the factoring wavefront works on block J + 1.  Two workgroup barriers per
+// block.  The factoring wavefront runs its own loop, so the registers of its
+// panel and of the others' tiles are never live together.  At the end every
+// block wavefront inverts its diagonal block of P S on the matrix cores.
+constexpr int MLB_PW = 17;   // LDS pitch of a 16-wide row
+template <int NBT>
+__host__ __device__ constexpr size_t mlu_blk_lds_bytes() {
+  // Lm[2], Lp[2] (16 NBT rows each), Li[2], one tile per wavefront, the
+  // pivot row; slot[2], rstep, pvt[2], live tiles[2], zero flag
+  return (size_t)(4 * 16 * NBT * MLB_PW + 2 * 16 * MLB_PW + (NBT + 1) * 16 * MLB_PW + 16) * 8 +
+         (size_t)(2 * 16 * NBT + 16 * NBT + 32 + 2 * NBT + 1) * 4;
+}
+
+template <int NBT>
+__global__ __launch_bounds__(64 * (NBT + 1)) void k_mlu_blk(KParams k, int mbeg) {
+  using Mq = Mf<double>;
+  using v4 = Mq::v4;
+  constexpr int NMAX = 16 * NBT, PW = MLB_PW, TS = 16 * PW, BUF = NMAX * PW;
+  constexpr int RS = (NMAX + 63) / 64;   // row slots per lane in the panel layout
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Lm = reinterpret_cast<double*>(smem_raw);   // [2][BUF] masked multipliers
+  double* Lp = Lm + 2 * BUF;                           // [2][BUF] the block being factored / factored
+  double* Li = Lp + 2 * BUF;                           // [2][TS] L11^{-1}
+  double* Gt = Li + 2 * TS;                            // [NBT + 1][TS] one tile per wavefront
+  double* rowbuf = Gt + (NBT + 1) * TS;                // [16] pivot row
+  int* slot = reinterpret_cast<int*>(rowbuf + 16);     // [2][NMAX] step of a block's pivot row, else -1
+  int* rstep = slot + 2 * NMAX;                        // [NMAX] step a row was chosen, -1 open, -2 padding
+  int* pvt = rstep + NMAX;                             // [2][16] pivot rows of a block
+  int* tlive = pvt + 32;                               // [2][NBT] tile has a row open before the block
+  int* zflag = tlive + 2 * NBT;
+
+  const MergeDesc Jm = k.merges[mbeg + blockIdx.x];
+  const int n = k.ku, mi = Jm.mif;
+  const int nbk = (n + 15) / 16;
+  double* S = k.sfac + (int64_t)mi * n * n;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const v4 zero = {0.0, 0.0, 0.0, 0.0};
+  if (tid == 0) *zflag = 0;
+  for (int r = tid; r < NMAX; r += blockDim.x) rstep[r] = r < n ? -1 : -2;
+
+  // (lane-derived indices go through opaque() so that the addresses are
+  // formed where they are used, not hoisted out of the block loop and kept)
+  auto mm = [&](const double* P, const v4& b, v4 d) __attribute__((always_inline)) -> v4 {
+    const int ln = opaque(lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d = Mq::mma(P[(ln & 15) * PW + Mq::row(ln, q)], b[q], d);
+    return d;
+  };
+  auto put = [&](double* P, const v4& v) __attribute__((always_inline)) {
+    const int ln = opaque(lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[Mq::row(ln, q) * PW + (ln & 15)] = v[q];
+  };
+  // (I + N)^{-1} = (I - N)(I + N^2)(I + N^4)(I + N^8) for a strictly
+  // triangular 16 x 16 N (nilpotent: N^16 = 0), G a tile of scratch
+  auto unit_inv = [&](const v4& N, double* G) __attribute__((always_inline)) -> v4 {
+    const int ln = opaque(lane);
+    v4 X, P = N;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) X[q] = (Mq::row(ln, q) == (ln & 15) ? 1.0 : 0.0) - N[q];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      put(G, P);
+      wave_lds_sync();
+      P = mm(G, P, zero);
+      wave_lds_sync();
+      put(G, P);
+      wave_lds_sync();
+      X = mm(G, X, X);
+      wave_lds_sync();
+    }
+    return X;
+  };
+
+  if (w == nbk) {
+    // ---- the factoring wavefront
+    __syncthreads();   // block 0 in Lp[0]
+    for (int J = 0; J < nbk; ++J) {
+      const int bb = J & 1, jb = min(16, n - 16 * J), s0 = 16 * J;
+      double* Lpb = Lp + bb * BUF;
+      double pr[RS][16];
+      unsigned rch = 0;   // which of this lane's rows are chosen (or padding)
+      {
+        const int ln = opaque(lane);
+#pragma unroll
+        for (int s = 0; s < RS; ++s) {
+          const int r = ln + 64 * s;
+          const bool in = r < NMAX;
+#pragma unroll
+          for (int c = 0; c < 16; ++c) pr[s][c] = in ? Lpb[r * PW + c] : 0.0;
+          if (!in || rstep[in ? r : 0] != -1) rch |= 1u << s;
+        }
+      }
+      static_for<0, 16>([&](auto TI) __attribute__((always_inline)) {
+        constexpr int t = decltype(TI)::value;
+        if (t < jb) {
+          double v[RS];
+          double best = -2.0;
+#pragma unroll
+          for (int s = 0; s < RS; ++s) {
+            double x = fabs(pr[s][t]);
+            if (x != x) x = -0.5;
+            if (rch & (1u << s)) x = -1.0;
+            v[s] = x;
+            best = fmax(best, x);
+          }
+          const double vmax = wave_max_f64(best);
+          int p = 0;
+#pragma unroll
+          for (int s = RS - 1; s >= 0; --s) {
+            const unsigned long long hit = __ballot(v[s] == vmax);
+            if (hit) p = 64 * s + (int)__builtin_ctzll(hit);
+          }
+          p = __builtin_amdgcn_readfirstlane(p);
+          const int sp = p >> 6, lp = p & 63;
+          const int l0 = opaque(lane);
+          // the pivot row through LDS (a uniform branch picks its slot)
+#pragma unroll
+          for (int s = 0; s < RS; ++s) {
+            if (s == sp) {
+              if (l0 == lp) {
+#pragma unroll
+                for (int c = t; c < 16; ++c) rowbuf[c] = pr[s][c];
+              }
+              if (l0 == lp) rch |= 1u << s;
+            }
+          }
+          wave_lds_sync();
+          const double piv = rowbuf[t];
+          if (l0 == 0) {
+            if (piv == 0.0) *zflag = 1;
+            rstep[p] = s0 + t;
+            pvt[bb * 16 + t] = p;
+          }
+          const double rp = piv != 0.0 ? 1.0 / piv : 0.0;
+          double l[RS];
+#pragma unroll
+          for (int s = 0; s < RS; ++s) {
+            const bool open = !(rch & (1u << s));
+            l[s] = open ? pr[s][t] * rp : 0.0;
+            if (open) pr[s][t] = l[s];
+          }
+#pragma unroll
+          for (int c = t + 1; c < 16; ++c) {
+            const double uc = rowbuf[c];
+#pragma unroll
+            for (int s = 0; s < RS; ++s) pr[s][c] = fma(-l[s], uc, pr[s][c]);
+          }
+          wave_lds_sync();
+        }
+      });
+      // the block's final values, the masked multipliers and the pivot steps
+      double* Lmb = Lm + bb * BUF;
+      if (lane < NBT) tlive[bb * NBT + lane] = 0;
+      wave_lds_sync();
+      {
+        const int ln = opaque(lane);
+#pragma unroll
+        for (int s = 0; s < RS; ++s) {
+          const int r = ln + 64 * s;
+          if (r < NMAX) {
+            const int rs_ = rstep[r];
+            const bool old = rs_ != -1 && rs_ < s0;
+            const int tt = rs_ >= s0 ? rs_ - s0 : 16;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+              Lpb[r * PW + c] = pr[s][c];
+              Lmb[r * PW + c] = (old || c >= tt) ? 0.0 : pr[s][c];
+            }
+            slot[bb * NMAX + r] = rs_ >= s0 ? tt : -1;
+            if (!old) tlive[bb * NBT + (r >> 4)] = 1;
+          }
+        }
+      }
+      wave_lds_sync();
+      // L11^{-1}, N(t, s) the multiplier of the block's pivot row t at step s < t
+      double* G = Gt + NBT * TS;   // this wavefront's own tile
+      v4 N;
+      {
+        const int ln = opaque(lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int tq = Mq::row(ln, q), c3 = ln & 15;
+          const int prow = tq < jb ? pvt[bb * 16 + tq] : 0;
+          N[q] = (c3 < tq && tq < jb) ? Lpb[prow * PW + c3] : 0.0;
+        }
+      }
+      const v4 X = unit_inv(N, G);
+      put(Li + bb * TS, X);
+      __syncthreads();   // block J published
+      if (J + 1 < nbk) __syncthreads();   // block J + 1 in Lp[bb ^ 1]
+    }
+  } else if (w < nbk) {
+    // ---- a block wavefront
+    double* G = Gt + w * TS;
+    v4 acc[NBT];
+    {
+      const int ln = opaque(lane);
+#pragma unroll
+      for (int R = 0; R < NBT; ++R)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * R + Mq::row(ln, q), c = 16 * w + (ln & 15);
+          acc[R][q] = (r < n && c < n) ? S[r + (int64_t)c * n] : 0.0;
+        }
+    }
+    if (w == 0) {
+#pragma unroll
+      for (int R = 0; R < NBT; ++R) put(Lp + R * TS, acc[R]);
+    }
+    __syncthreads();   // block 0 in Lp[0]
+    // block J's rank-16 update of this wavefront's tiles (buffer b)
+    auto update = [&](int J, int b) __attribute__((always_inline)) {
+      const int jb = min(16, n - 16 * J);
+      const double* Lmb = Lm + b * BUF;
+      const int* sl = slot + b * NMAX;
+      {
+        // the block's pivot rows of this wavefront's columns into G (row = step)
+        const int ln = opaque(lane), c4 = ln & 15;
+#pragma unroll
+        for (int R = 0; R < NBT; ++R)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int t = sl[16 * R + Mq::row(ln, q)];
+            if (t >= 0) G[t * PW + c4] = acc[R][q];
+          }
+      }
+      wave_lds_sync();
+      v4 a12;
+      {
+        const int ln = opaque(lane), c4 = ln & 15;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int tq = Mq::row(ln, q);
+          a12[q] = tq < jb ? G[tq * PW + c4] : 0.0;
+        }
+      }
+      const v4 u12 = mm(Li + b * TS, a12, zero);
+      {
+        const int ln = opaque(lane);
+#pragma unroll
+        for (int R = 0; R < NBT; ++R) {
+          if (R < nbk && tlive[b * NBT + R]) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[R] = Mq::mma(-Lmb[(16 * R + (ln & 15)) * PW + Mq::row(ln, q)], u12[q], acc[R]);
+          }
+        }
+      }
+      wave_lds_sync();
+    };
+    for (int J = 0; J < nbk; ++J) {
+      const int b = J & 1;
+      __syncthreads();   // block J published
+      if (w == J) {
+        // the factored block back (whole vectors: the values before are dead)
+        const int ln = opaque(lane);
+        const double* Lpb = Lp + b * BUF;
+#pragma unroll
+        for (int R = 0; R < NBT; ++R) {
+          const double* Lr = Lpb + (16 * R) * PW + (ln & 15);
+          acc[R] = v4{Lr[Mq::row(ln, 0) * PW], Lr[Mq::row(ln, 1) * PW], Lr[Mq::row(ln, 2) * PW],
+                      Lr[Mq::row(ln, 3) * PW]};
+        }
+      } else if (w == J + 1) {
+        update(J, b);
+#pragma unroll
+        for (int R = 0; R < NBT; ++R) put(Lp + (b ^ 1) * BUF + R * TS, acc[R]);
+      }
+      if (J + 1 < nbk) __syncthreads();   // block J + 1 in Lp[b ^ 1]
+      if (w > J + 1) update(J, b);        // meanwhile block J + 1 is factored
+    }
+    // P S = L U packed: row rstep[r] of the output is row r of S
+    {
+      const int ln = opaque(lane);
+#pragma unroll
+      for (int R = 0; R < NBT; ++R)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * R + Mq::row(ln, q), c = 16 * w + (ln & 15);
+          if (r < n && c < n) S[rstep[r] + (int64_t)c * n] = acc[R][q];
+        }
+    }
+    // the inverses of the unit lower and of the upper triangle of diagonal
+    // block w of P S (the identity beyond the order), for the sweeps
+    {
+      const int ln = opaque(lane), c4 = ln & 15;
+#pragma unroll
+      for (int R = 0; R < NBT; ++R)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * R + Mq::row(ln, q);
+          if (r < n) {
+            const int i = rstep[r];
+            if ((i >> 4) == w) G[(i & 15) * PW + c4] = acc[R][q];
+          }
+        }
+      wave_lds_sync();
+      v4 Dg;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i16 = Mq::row(ln, q);
+        const bool in = 16 * w + i16 < n && 16 * w + c4 < n;
+        Dg[q] = in ? G[i16 * PW + c4] : (i16 == c4 ? 1.0 : 0.0);
+      }
+      wave_lds_sync();
+      put(G, Dg);
+      wave_lds_sync();
+      // lane t < 16: column t of L^{-1} by forward substitution; lane 16 + t:
+      // column t of U^{-1} by back substitution (the block read from LDS)
+      double* Dv = k.sdinv + ((int64_t)mi * ((n + 15) / 16) + w) * dinv_stride();
+      const int t = ln & 15;
+      double x[16];
+      if (ln < 16) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          double a = (r == t) ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = 0; q < r; ++q) a = fma(-G[r * PW + q], x[q], a);
+          x[r] = a;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Dv[r * 16 + t] = x[r];
+      } else if (ln < 32) {
+#pragma unroll
+        for (int r = 15; r >= 0; --r) {
+          double a = (r == t) ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = r + 1; q < 16; ++q) a = fma(-G[r * PW + q], x[q], a);
+          x[r] = a / G[r * PW + r];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Dv[256 + r * 16 + t] = x[r];
+      }
+    }
+  } else {
+    // ---- wavefronts beyond the blocks (n = 0): the same barriers
+    __syncthreads();
+    for (int J = 0; J < nbk; ++J) {
+      __syncthreads();
+      if (J + 1 < nbk) __syncthreads();
+    }
+  }
+  __syncthreads();
+  // the permutation (row i of P S is row perm[i] of S)
+  int* perm = k.sperm + (int64_t)mi * n;
+  for (int r = tid; r < n; r += blockDim.x) perm[rstep[r]] = r;
+  if (tid == 0 && *zflag) atomicMin(&k.status->iface, (unsigned long long)(mi + 1));
+}
+
 // ------------------------------------------------------- beta, delta solves
 // LDS doubles of k_mtrsm<HT>.
 template <int HT>
@@ -653,13 +1021,118 @@ __device__ inline void wg_gemm_nr(int M, int N, int K, double alpha, GM A, GM B,
   __syncthreads();
 }
 
-// Products of the reduced solve: one column with per-thread dot products,
-// up to 16 columns on one MFMA column tile, more in groups of 16.
+// LDS doubles every reduced-solve launch provides (at least).
+constexpr int kMsolveLds = 2 * 16 * 65;
+
+// Sum of v over the wavefront, returned uniformly: row shifts within rows of
+// 16 lanes, then the row broadcasts, into lane 63 (lanes without a source
+// add zero); a fixed order, so the result repeats bitwise.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add_step(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  const int slo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+  const int shi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+  return v + __longlong_as_double(((long long)shi << 32) | (long long)(unsigned int)slo);
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v = dpp_add_step<0x111, 0xf>(v);   // row_shr:1
+  v = dpp_add_step<0x112, 0xf>(v);   // row_shr:2
+  v = dpp_add_step<0x114, 0xf>(v);   // row_shr:4
+  v = dpp_add_step<0x118, 0xf>(v);   // row_shr:8
+  v = dpp_add_step<0x142, 0xa>(v);   // row_bcast:15
+  v = dpp_add_step<0x143, 0xc>(v);   // row_bcast:31
+  return lane_read(v, 63);
+}
+
+// y = alpha A x + beta y for one right-hand side, bound by the latency of
+// reading A (a k x k block of the reduced system): x is staged in LDS and
+// every lane keeps up to 40 loads of A in flight before using them.
+// Column-major A (rs = 1): lanes run over rows, the four wavefronts over
+// quarters of K, partial sums combined through LDS; row-major A (cs = 1):
+// a wavefront takes 8 rows at a time with its lanes across K, then sums each
+// row over the wavefront.  Needs K + 4 M <= kMsolveLds doubles of LDS (the
+// caller checks); starts after and ends with a barrier.
+__device__ inline void wg_gemv(int M, int K, double alpha, GM A, const double* x, double beta, double* y,
+                               double* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* xl = lds;
+  double* part = lds + K;
+  for (int kk = tid; kk < K; kk += NT) xl[kk] = gld(x + kk);
+  __syncthreads();
+  constexpr int LB = 40;   // loads in flight per lane
+  if (A.rs == 1) {
+    const int kq = (K + 3) / 4, nrc = (M + 63) / 64;
+    for (int it = wave; it < 4 * nrc; it += NT / 64) {
+      const int q = it % 4, i = 64 * (it / 4) + lane;
+      const int k0 = q * kq, k1 = min(K, k0 + kq);
+      const bool row_ok = i < M;
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int kb = k0; kb < k1; kb += LB) {
+        double v[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int kk = kb + u;
+          v[u] = (row_ok && kk < k1) ? gld(A.p + i + (int64_t)kk * A.cs) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int kk = kb + u;
+          if (kk < k1) a4[u & 3] = fma(v[u], sld(xl + kk), a4[u & 3]);
+        }
+      }
+      if (row_ok) part[q * M + i] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    }
+    __syncthreads();
+    for (int i = tid; i < M; i += NT) {
+      const double sum = (part[i] + part[M + i]) + (part[2 * M + i] + part[3 * M + i]);
+      y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * sum;
+    }
+  } else {
+    constexpr int RW = 8;                  // rows per wavefront pass
+    const int nkb = (K + 63) / 64;         // loads per row and lane
+    for (int i0 = RW * wave; i0 < M; i0 += RW * (NT / 64)) {
+      double acc[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) acc[r] = 0.0;
+      for (int kb0 = 0; kb0 < nkb; kb0 += LB / RW) {
+        double v[RW][LB / RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+          for (int u = 0; u < LB / RW; ++u) {
+            const int kk = 64 * (kb0 + u) + lane, i = i0 + r;
+            v[r][u] = (i < M && kk < K) ? gld(A.p + (int64_t)i * A.rs + kk) : 0.0;
+          }
+#pragma unroll
+        for (int u = 0; u < LB / RW; ++u) {
+          const int kk = 64 * (kb0 + u) + lane;
+          const double xv = kk < K ? sld(xl + kk) : 0.0;
+#pragma unroll
+          for (int r = 0; r < RW; ++r) acc[r] = fma(v[r][u], xv, acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const double sum = wave_sum_f64(acc[r]);
+        const int i = i0 + r;
+        if (lane == 0 && i < M) y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * sum;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Products of the reduced solve: one column on the latency-bound gemv (or
+// per-thread dot products where its LDS does not suffice), up to 16 columns
+// on one MFMA column tile, more in groups of 16.
 __device__ __forceinline__ void mgemm_any(int M, int N, int K, double alpha, GM A, GM B, double beta, double* C,
                                           int64_t ldc, double* lds) {
-  (void)lds;
   if (N == 1) {
-    wg_gemm_nr(M, N, K, alpha, A, B, beta, C, ldc);
+    if (B.rs == 1 && (A.rs == 1 || A.cs == 1) && K + 4 * M <= kMsolveLds)
+      wg_gemv(M, K, alpha, A, B.p, beta, C, lds);
+    else
+      wg_gemm_nr(M, N, K, alpha, A, B, beta, C, ldc);
     return;
   }
   for (int c0 = 0; c0 < N; c0 += 16) {
@@ -861,6 +1334,9 @@ int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
   const size_t lu_lds = (size_t)mlu_lds_elems(k.ku) * 8;
   const size_t tr_lds = (size_t)mtrsm_lds_elems<HT>() * 8 + 2048;
   allow_lds_m(k_mlu, lu_lds);
+  allow_lds_m(k_mlu_blk<4>, mlu_blk_lds_bytes<4>());
+  allow_lds_m(k_mlu_blk<8>, mlu_blk_lds_bytes<8>());
+  allow_lds_m(k_mlu_blk<10>, mlu_blk_lds_bytes<10>());
   allow_lds_m(k_mtrsm<HT>, tr_lds);
   const int ncg = (kmax + 63) / 64;
   // fused products: rows up to kmax, kw = kl + ku columns, 64 x 64 tiles
@@ -875,8 +1351,13 @@ int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
     }
     {
       ProfScope ps("k_mlu", st);
-      if (k.ku <= 128)
-        hipLaunchKernelGGL((k_mlu_reg<16, 2>), dim3(cnt), dim3(NWR * 64), 0, st, k, beg);
+      const int nw = (k.ku + 15) / 16 + 1;   // block wavefronts and the factoring one
+      if (k.ku <= 64)
+        hipLaunchKernelGGL((k_mlu_blk<4>), dim3(cnt), dim3(64 * nw), mlu_blk_lds_bytes<4>(), st, k, beg);
+      else if (k.ku <= 128)
+        hipLaunchKernelGGL((k_mlu_blk<8>), dim3(cnt), dim3(64 * nw), mlu_blk_lds_bytes<8>(), st, k, beg);
+      else if (k.ku <= 160)
+        hipLaunchKernelGGL((k_mlu_blk<10>), dim3(cnt), dim3(64 * nw), mlu_blk_lds_bytes<10>(), st, k, beg);
       else if (k.ku <= 192)
         hipLaunchKernelGGL((k_mlu_reg<24, 3>), dim3(cnt), dim3(NWR * 64), 0, st, k, beg);
       else
@@ -904,7 +1385,7 @@ int run_mfactor(const KParams& k, const LaunchCfg& c, hipStream_t st) {
 
 template <int HT>
 int run_msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, bool trans) {
-  const size_t lds = (size_t)(tile_lds_elems(HT) > 2 * 16 * 65 ? tile_lds_elems(HT) : 2 * 16 * 65) * 8 + 2048;
+  const size_t lds = (size_t)(tile_lds_elems(HT) > kMsolveLds ? tile_lds_elems(HT) : kMsolveLds) * 8 + 2048;
   allow_lds_m(k_mup<HT>, lds);
   allow_lds_m(k_mtdown<HT>, lds);
   allow_lds_m(k_mdown, lds);
@@ -945,7 +1426,7 @@ int run_msolve(const KParams& k, const LaunchCfg& c, hipStream_t st, int nrhs, b
 template <int HT>
 int run_msolve_level_batch(const BatchArgs& ba, hipStream_t st, int nitems, bool trans, bool up) {
   if (nitems <= 0) return 0;
-  const size_t lds = (size_t)(tile_lds_elems(HT) > 2 * 16 * 65 ? tile_lds_elems(HT) : 2 * 16 * 65) * 8 + 2048;
+  const size_t lds = (size_t)(tile_lds_elems(HT) > kMsolveLds ? tile_lds_elems(HT) : kMsolveLds) * 8 + 2048;
   const int kind = trans ? (up ? 2 : 3) : (up ? 0 : 1);
   switch (kind) {
     case 0: {
