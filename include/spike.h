@@ -213,7 +213,11 @@ SPIKE_API int spike_handle_plan(spike_handle h, spike_plan_info *out);
  * the library with HIP events recorded on the launch stream.
  * spike_profile_report() waits for the recorded events and writes, per
  * kernel name, the number of launches and their summed duration (up to cap
- * entries; *count receives the number of distinct kernels). */
+ * entries; *count receives the number of distinct kernels).
+ * spike_profile_only(name) restricts the brackets to launches of the kernel
+ * of that name (NULL or "" for all), so that a timed loop carries the events
+ * of one kernel only; it applies from the next spike_profile_enable(1).
+ * Errors: -1 name longer than 47 characters. */
 typedef struct spike_kernel_time {
     char name[48];
     int32_t calls;
@@ -221,6 +225,7 @@ typedef struct spike_kernel_time {
 } spike_kernel_time;
 
 SPIKE_API int spike_profile_enable(int on);
+SPIKE_API int spike_profile_only(const char *name);
 SPIKE_API int spike_profile_report(spike_kernel_time *out, int cap, int *count);
 
 /* Complex banded systems (the complex precisions of the paper's library,
@@ -388,9 +393,13 @@ typedef struct spike_graph_s *spike_graph;
  * constant K is measured here rather than assumed).  Times factorisation +
  * solve of candidate plans on the caller's matrix and device: partition
  * counts around the number of compute units and the planner's default, equal
- * sizing; estimates K = (solve ms * max(kl,ku)) / (factor ms * nrhs) from the
- * fastest one and times that p again with R13 sizing at that K.  Blocks the
- * host until each timing is done.
+ * sizing, each with the balanced tree and, where the count admits it, the
+ * paper's 2^m + r thread layout; estimates K = (solve ms * max(kl,ku)) /
+ * (factor ms * nrhs) from the fastest one and times that p again with R13
+ * sizing at that K.  Blocks the host until each timing is done.  Results are
+ * kept in a process-wide cache keyed by (n, kl, ku, floor(log2 nrhs),
+ * precision, pivot): a later call with the same key returns the cached
+ * options and timings without timing anything (out->cached = 1).
  *   dAB, ldab   the matrix (as spike_factor)
  *   nrhs        columns of the solves to tune for (>= 1)
  *   base        options to start from (NULL: defaults); p and sizing are
@@ -408,7 +417,22 @@ typedef struct spike_tune_result {
     double solve_ms;
     double K;
     int32_t candidates;
+    int32_t cached;     /* 1: taken from the tuning cache, nothing was timed */
 } spike_tune_result;
+
+/* The tuning cache (a project addition for serving: a tuned plan is reused
+ * for every later system of the same shape).  spike_tune_cache_clear empties
+ * it; spike_tune_cache_save writes it to a text file, one entry per line:
+ *   n kl ku log2_nrhs precision pivot p sizing tree K nrhs_hint r12 r13
+ *   factor_ms solve_ms candidates
+ * and spike_tune_cache_load merges such a file into it (an entry replaces
+ * one of the same key).  spike_tune_cache_size reports the entry count.
+ * Errors: -1 path NULL, -2 the file cannot be opened, -3 a malformed line
+ * (entries before it are kept). */
+SPIKE_API int spike_tune_cache_clear(void);
+SPIKE_API int spike_tune_cache_size(void);
+SPIKE_API int spike_tune_cache_save(const char *path);
+SPIKE_API int spike_tune_cache_load(const char *path);
 
 SPIKE_API int spike_autotune_workspace_size(int64_t n, int32_t kl, int32_t ku,
                                             const spike_opts *base, size_t *bytes);

@@ -4,7 +4,12 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 #include <new>
 
@@ -339,13 +344,36 @@ std::vector<spike_opts> tune_candidates(int64_t n, int32_t kl, int32_t ku, const
     bool dup = false;
     for (auto& o : out) dup = dup || o.p == p;
     if (dup) continue;
-    spike_opts o = base;
-    o.p = p;
-    o.sizing = 0;
-    spike::Plan pl;
-    if (spike::make_plan(n, kl, ku, o, pl) == 0) out.push_back(o);
+    for (int tree : {0, 1}) {
+      // the paper's layout differs from the balanced tree when p is not a
+      // power of two (and is admissible for it)
+      if (tree == 1 && (p & (p - 1)) == 0) continue;
+      spike_opts o = base;
+      o.p = p;
+      o.sizing = 0;
+      o.tree = tree;
+      spike::Plan pl;
+      if (spike::make_plan(n, kl, ku, o, pl) == 0) out.push_back(o);
+    }
   }
   return out;
+}
+
+// ---- the tuning cache
+using TuneKey = std::tuple<int64_t, int32_t, int32_t, int32_t, int32_t, int32_t>;
+std::mutex g_tune_mu;
+std::map<TuneKey, spike_tune_result> g_tune;
+
+int32_t log2_floor(int32_t v) {
+  int32_t l = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++l;
+  }
+  return l;
+}
+TuneKey tune_key(int64_t n, int32_t kl, int32_t ku, int32_t nrhs, const spike_opts& o) {
+  return TuneKey{n, kl, ku, log2_floor(std::max(1, nrhs)), o.precision, o.pivot};
 }
 
 }  // namespace
@@ -705,6 +733,17 @@ int spike_autotune(int64_t n, int32_t kl, int32_t ku, const double* dAB, int64_t
   else spike::default_opts(&b);
   b.nrhs_hint = nrhs;
   if (b.nrhs_max < nrhs) b.nrhs_max = nrhs;
+  const TuneKey key = tune_key(n, kl, ku, nrhs, b);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *out = it->second;
+      out->opts.nrhs_max = std::max(out->opts.nrhs_max, b.nrhs_max);
+      out->cached = 1;
+      return 0;
+    }
+  }
   hipEvent_t ev[3];
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) return SPIKE_ERR_HIP - (int)hipErrorOutOfMemory;
@@ -778,7 +817,81 @@ int spike_autotune(int64_t n, int32_t kl, int32_t ku, const double* dAB, int64_t
   out->solve_ms = bs;
   out->K = K;
   out->candidates = ncand;
+  out->cached = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = *out;
+  }
   return 0;
+}
+
+int spike_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return 0;
+}
+
+int spike_tune_cache_size(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+int spike_tune_cache_save(const char* path) {
+  if (!path) return -1;
+  std::FILE* f = std::fopen(path, "w");
+  if (!f) return -2;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : g_tune) {
+    const TuneKey& k = kv.first;
+    const spike_tune_result& r = kv.second;
+    std::fprintf(f, "%lld %d %d %d %d %d %d %d %d %.17g %d %.17g %.17g %.17g %.17g %d\n",
+                 (long long)std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                 std::get<5>(k), r.opts.p, r.opts.sizing, r.opts.tree, r.opts.K, r.opts.nrhs_hint, r.opts.r12,
+                 r.opts.r13, r.factor_ms, r.solve_ms, r.candidates);
+  }
+  std::fclose(f);
+  return 0;
+}
+
+int spike_tune_cache_load(const char* path) {
+  if (!path) return -1;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return -2;
+  char line[512];
+  int rc = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    long long n = 0;
+    int kl, ku, lg, prec, piv, p, sizing, tree, nh, cand;
+    double K, r12, r13, fm, sm;
+    if (line[0] == '\n' || line[0] == '#') continue;
+    if (std::sscanf(line, "%lld %d %d %d %d %d %d %d %d %lg %d %lg %lg %lg %lg %d", &n, &kl, &ku, &lg, &prec, &piv,
+                    &p, &sizing, &tree, &K, &nh, &r12, &r13, &fm, &sm, &cand) != 16 ||
+        n < 1 || kl < 0 || ku < 0 || lg < 0 || lg > 30 || (prec != 0 && prec != 1) || (piv != 0 && piv != 1) ||
+        p < 1 || sizing < 0 || sizing > 2 || (tree != 0 && tree != 1)) {
+      rc = -3;
+      break;
+    }
+    spike_tune_result r;
+    std::memset(&r, 0, sizeof(r));
+    spike::default_opts(&r.opts);
+    r.opts.p = p;
+    r.opts.pivot = piv;
+    r.opts.precision = prec;
+    r.opts.sizing = sizing;
+    r.opts.tree = tree;
+    r.opts.K = K;
+    r.opts.nrhs_hint = nh;
+    r.opts.nrhs_max = std::max(r.opts.nrhs_max, 1 << lg);
+    r.opts.r12 = r12;
+    r.opts.r13 = r13;
+    r.factor_ms = fm;
+    r.solve_ms = sm;
+    r.candidates = cand;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[TuneKey{(int64_t)n, kl, ku, lg, prec, piv}] = r;
+  }
+  std::fclose(f);
+  return rc;
 }
 
 int spike_destroy(spike_handle h) {

@@ -22,6 +22,8 @@ struct Rec {
 
 std::atomic<bool> g_on{false};
 std::mutex g_mu;
+std::string g_only;    // the one kernel to bracket, empty for all
+std::string g_armed;   // g_only as of the last spike_profile_enable
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -53,6 +55,7 @@ int prof_begin(const char* name, hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_armed.empty() && g_armed != name) return -1;
   Rec r{name, take_event(), take_event()};
   if (!r.start || !r.end) return -1;
   hipEventRecord(r.start, st);
@@ -72,7 +75,15 @@ extern "C" {
 int spike_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(spike::g_mu);
   spike::recycle_all();
+  spike::g_armed = spike::g_only;
   spike::g_on.store(on != 0);
+  return 0;
+}
+
+int spike_profile_only(const char* name) {
+  if (name && std::strlen(name) > 47) return -1;
+  std::lock_guard<std::mutex> lk(spike::g_mu);
+  spike::g_only = name ? name : "";
   return 0;
 }
 

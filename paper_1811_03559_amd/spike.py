@@ -51,7 +51,7 @@ class KernelTime(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("opts", Opts), ("factor_ms", _c_dbl), ("solve_ms", _c_dbl), ("K", _c_dbl),
-                ("candidates", _c_i32)]
+                ("candidates", _c_i32), ("cached", _c_i32)]
 
 
 class KrylovOpts(ctypes.Structure):
@@ -187,6 +187,16 @@ def lib():
             L.spike_sweep_counts.argtypes = [_c_p, ctypes.POINTER(ctypes.c_uint64)]
             L.spike_profile_enable.restype = ctypes.c_int
             L.spike_profile_enable.argtypes = [ctypes.c_int]
+            L.spike_profile_only.restype = ctypes.c_int
+            L.spike_profile_only.argtypes = [ctypes.c_char_p]
+            L.spike_tune_cache_clear.restype = ctypes.c_int
+            L.spike_tune_cache_clear.argtypes = []
+            L.spike_tune_cache_size.restype = ctypes.c_int
+            L.spike_tune_cache_size.argtypes = []
+            L.spike_tune_cache_save.restype = ctypes.c_int
+            L.spike_tune_cache_save.argtypes = [ctypes.c_char_p]
+            L.spike_tune_cache_load.restype = ctypes.c_int
+            L.spike_tune_cache_load.argtypes = [ctypes.c_char_p]
             L.spike_profile_report.restype = ctypes.c_int
             L.spike_profile_report.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int,
                                                ctypes.POINTER(ctypes.c_int)]
@@ -205,6 +215,14 @@ def profile_enable(on=True):
     rc = lib().spike_profile_enable(1 if on else 0)
     if rc != 0:
         raise SpikeError("spike_profile_enable", rc)
+
+
+def profile_only(name=None):
+    """Bracket only the launches of kernel `name` (None: every kernel) from
+    the next profile_enable(True) on (spike_profile_only)."""
+    rc = lib().spike_profile_only(name.encode() if name else None)
+    if rc != 0:
+        raise SpikeError("spike_profile_only", rc)
 
 
 def profile_report():
@@ -600,7 +618,27 @@ def autotune(ab, kl, ku, nrhs=1, stream=None, **base):
             "K": r.K, "nrhs_hint": r.nrhs_hint,
             "nrhs_max": r.nrhs_max, "tree": "paper" if r.tree else "balanced"}
     return opts, {"factor_ms": res.factor_ms, "solve_ms": res.solve_ms, "K": res.K,
-                  "candidates": res.candidates}
+                  "candidates": res.candidates, "cached": bool(res.cached)}
+
+
+def tune_cache_clear():
+    lib().spike_tune_cache_clear()
+
+
+def tune_cache_size():
+    return int(lib().spike_tune_cache_size())
+
+
+def tune_cache_save(path):
+    rc = lib().spike_tune_cache_save(str(path).encode())
+    if rc != 0:
+        raise SpikeError("spike_tune_cache_save", rc)
+
+
+def tune_cache_load(path):
+    rc = lib().spike_tune_cache_load(str(path).encode())
+    if rc != 0:
+        raise SpikeError("spike_tune_cache_load", rc)
 
 
 class Server:

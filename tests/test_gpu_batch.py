@@ -145,8 +145,10 @@ def test_autotune_returns_a_working_plan():
     n, k = 60000, 16
     ab = inputs.band_dominant(n, k, k, inputs.rng_for(5600), diag_mult=1.05, diag_add=0.0)
     dab = torch.from_numpy(ab).cuda()
+    spike.tune_cache_clear()
     opts, res = spike.autotune(dab, k, k, nrhs=2)
     assert res["candidates"] >= 2 and res["K"] > 0, res
+    assert not res["cached"]
     assert res["factor_ms"] > 0 and res["solve_ms"] > 0, res
     F = inputs.rhs(n, 2, inputs.rng_for(5601))
     fac = spike.Factorization(dab, k, k, **opts)
@@ -155,3 +157,36 @@ def test_autotune_returns_a_working_plan():
     torch.cuda.synchronize()
     check(ab, k, k, F, B.cpu().numpy(), pivot=False)
     fac.close()
+
+
+def test_autotune_cache_reuses_and_reloads(tmp_path):
+    """A second autotune of the same shape (n, kl, ku, log2 nrhs, precision,
+    pivot) comes from the cache with the same options; after clearing, the
+    file written by tune_cache_save restores it; a new shape is tuned."""
+    import torch
+    from paper_1811_03559_amd import spike
+    n, k = 40000, 8
+    ab = inputs.band_dominant(n, k, k, inputs.rng_for(5700), diag_mult=1.05, diag_add=0.0)
+    dab = torch.from_numpy(ab).cuda()
+    spike.tune_cache_clear()
+    o1, r1 = spike.autotune(dab, k, k, nrhs=3)
+    assert not r1["cached"] and spike.tune_cache_size() == 1
+    o2, r2 = spike.autotune(dab, k, k, nrhs=2)   # same log2 bucket
+    assert r2["cached"] and o2["p"] == o1["p"] and o2["tree"] == o1["tree"] and o2["sizing"] == o1["sizing"]
+    assert r2["factor_ms"] == r1["factor_ms"]
+    path = tmp_path / "cache.txt"
+    spike.tune_cache_save(path)
+    spike.tune_cache_clear()
+    spike.tune_cache_load(path)
+    o3, r3 = spike.autotune(dab, k, k, nrhs=3)
+    assert r3["cached"] and o3["p"] == o1["p"] and o3["tree"] == o1["tree"]
+    o4, r4 = spike.autotune(dab, k, k, nrhs=16)   # another bucket
+    assert not r4["cached"] and spike.tune_cache_size() == 2
+    F = inputs.rhs(n, 3, inputs.rng_for(5701))
+    fac = spike.Factorization(dab, k, k, **o3)
+    B = torch.from_numpy(F.copy()).cuda()
+    fac.solve_(B)
+    torch.cuda.synchronize()
+    check(ab, k, k, F, B.cpu().numpy(), pivot=False)
+    fac.close()
+    spike.tune_cache_clear()

@@ -352,3 +352,44 @@ def test_pivoting_limited_to_32_column_panels():
     assert e.value.code == -4
     # FP32 factors halve the LDS per element: 32-column panels still fit
     assert spike.plan_query(n, 200, 200, p=8, pivot=True, precision="mixed")["p"] == 8
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """The tuning cache's text format: load merges entries, save writes them
+    back (the same 16 fields), a malformed line is refused after the good
+    lines before it, a missing file is an error."""
+    spike.tune_cache_clear()
+    assert spike.tune_cache_size() == 0
+    src = tmp_path / "tune.txt"
+    src.write_text("# n kl ku log2_nrhs precision pivot p sizing tree K nrhs_hint r12 r13 f_ms s_ms cand\n"
+                   "1000000 160 160 0 0 0 256 0 0 0 1 0 0 13.5 5.25 6\n"
+                   "500000 64 64 4 0 1 250 1 1 0.75 16 0 0 40 15 7\n")
+    spike.tune_cache_load(src)
+    assert spike.tune_cache_size() == 2
+    out = tmp_path / "out.txt"
+    spike.tune_cache_save(out)
+    rows = sorted(line.split() for line in out.read_text().splitlines())
+    assert len(rows) == 2 and all(len(r) == 16 for r in rows)
+    by_n = {r[0]: r for r in rows}
+    assert by_n["1000000"][6:9] == ["256", "0", "0"] and float(by_n["1000000"][13]) == 13.5
+    assert by_n["500000"][4:9] == ["0", "1", "250", "1", "1"] and float(by_n["500000"][9]) == 0.75
+    spike.tune_cache_clear()
+    spike.tune_cache_load(out)
+    assert spike.tune_cache_size() == 2
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1000 4 4 0 0 0 3 0 0 0 1 0 0 1 1 1\n1000 4 4 0 0 0 3 7 0 0 1 0 0 1 1 1\n")
+    spike.tune_cache_clear()
+    with pytest.raises(spike.SpikeError) as e:
+        spike.tune_cache_load(bad)
+    assert e.value.code == -3
+    assert spike.tune_cache_size() == 1
+    with pytest.raises(spike.SpikeError) as e:
+        spike.tune_cache_load(tmp_path / "missing.txt")
+    assert e.value.code == -2
+    spike.tune_cache_clear()
+
+
+def test_profile_only_name_length():
+    assert spike.lib().spike_profile_only(b"x" * 48) == -1
+    spike.profile_only("k_flu")
+    spike.profile_only(None)
