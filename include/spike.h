@@ -187,6 +187,25 @@ SPIKE_API int spike_factor(int64_t n, int32_t kl, int32_t ku, const double *dAB,
                  int64_t ldab, const spike_opts *opts, void *dWork,
                  size_t work_bytes, hipStream_t stream, spike_handle *out);
 
+/* Batched factorisation: the factor stage of count systems, each as
+ * spike_factor would factor it (its own n, bands, options, workspace and
+ * handle), with the systems that share a kernel configuration (non-pivoting
+ * factors on the matrix-core block LU, equal kl and ku, the same precision)
+ * factored by common launches: one launch per kernel of the stage covers up
+ * to 32 of them, so that many small systems fill the GPU together (the
+ * batched form of the factorisation stage, section "Recursive SPIKE").
+ * Other systems are factored one after the other on the same stream.
+ *   n, kl, ku, dAB, ldab, dWork, work_bytes, out   arrays of count entries,
+ *               each as the argument of the same name of spike_factor
+ *   opts        array of count options, or NULL for the defaults
+ * Returns 0, or the spike_factor error code of the first system with a bad
+ * argument (nothing is launched and no handle is created), -11 count < 0,
+ * -12 an array NULL, -1000-hipError. */
+SPIKE_API int spike_factor_batch(int32_t count, const int64_t *n, const int32_t *kl, const int32_t *ku,
+                                 const double *const *dAB, const int64_t *ldab, const spike_opts *opts,
+                                 void *const *dWork, const size_t *work_bytes, hipStream_t stream,
+                                 spike_handle *out);
+
 /* Solve A X = F in place: dB (device, column-major n x nrhs, ldb >= n) holds
  * F on entry and X on exit.  Uses the handle's workspace; calls on one handle
  * must be ordered (same stream or synchronised).  If the factorisation

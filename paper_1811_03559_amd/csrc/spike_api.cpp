@@ -460,6 +460,104 @@ int spike_factor(int64_t n, int32_t kl, int32_t ku, const double* dAB, int64_t l
   return 0;
 }
 
+int spike_factor_batch(int32_t count, const int64_t* n, const int32_t* kl, const int32_t* ku,
+                       const double* const* dAB, const int64_t* ldab, const spike_opts* opts, void* const* dWork,
+                       const size_t* work_bytes, hipStream_t stream, spike_handle* out) {
+  if (count < 0) return -11;
+  if (count == 0) return 0;
+  if (!n || !kl || !ku || !dAB || !ldab || !dWork || !work_bytes || !out) return -12;
+  // every system's arguments first, so that nothing starts on an error
+  std::vector<spike::Plan> plans(count);
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 0) return -1;
+    if (kl[i] < 0) return -2;
+    if (ku[i] < 0) return -3;
+    if (dAB[i] == nullptr && n[i] > 0) return -4;
+    if (ldab[i] < (int64_t)kl[i] + ku[i] + 1) return -5;
+    if (plan_for(n[i], kl[i], ku[i], opts ? &opts[i] : nullptr, plans[i])) return -6;
+    if (dWork[i] == nullptr || (reinterpret_cast<uintptr_t>(dWork[i]) & 255u) != 0) return -7;
+    if (work_bytes[i] < plans[i].total) return -8;
+  }
+  std::vector<spike_handle> hs(count, nullptr);
+  auto fail = [&](int e) {
+    for (auto& h : hs)
+      if (h) {
+        h->magic = 0;
+        delete h;
+        h = nullptr;
+      }
+    return e;
+  };
+  for (int i = 0; i < count; ++i) {
+    spike_handle h = new (std::nothrow) spike_handle_s();
+    if (!h) return fail(SPIKE_ERR_HIP - (int)hipErrorOutOfMemory);
+    hs[i] = h;
+    h->magic = kMagic;
+    h->plan = std::move(plans[i]);
+    h->ws = static_cast<char*>(dWork[i]);
+    fill_params(h, dAB[i], ldab[i]);
+    if (int e = upload(h, stream)) return fail(e);
+  }
+  // systems sharing the kernel configuration of the batched factor stage
+  std::vector<std::vector<int>> groups;
+  std::vector<uint64_t> keys;
+  std::vector<int> rest;
+  for (int i = 0; i < count; ++i) {
+    const spike_handle h = hs[i];
+    const spike::LaunchCfg& c = h->cfg;
+    const bool ok = h->plan.n > 0 && !h->plan.pivot && c.flu && c.fast && (h->plan.p == 1 || c.mfast) &&
+                    !h->kp.sweeps;
+    if (!ok) {
+      rest.push_back(i);
+      continue;
+    }
+    const uint64_t key = ((uint64_t)c.fp32 << 56) | ((uint64_t)c.ht << 48) |
+                         ((uint64_t)(c.mfast ? c.mht : 0) << 40) | ((uint64_t)(uint32_t)kl[i] << 20) |
+                         (uint64_t)(uint32_t)ku[i];
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != key) ++g;
+    if (g == keys.size()) {
+      keys.push_back(key);
+      groups.emplace_back();
+    }
+    groups[g].push_back(i);
+  }
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const std::vector<int>& v = groups[g];
+    for (size_t b0 = 0; b0 < v.size(); b0 += spike::kMaxBatch) {
+      const int cnt = (int)std::min<size_t>(spike::kMaxBatch, v.size() - b0);
+      spike::BatchArgs ba;
+      std::memset(&ba, 0, sizeof(ba));
+      ba.nsys = cnt;
+      std::vector<int> p(cnt);
+      std::vector<const std::vector<int>*> lo(cnt);
+      for (int s = 0; s < cnt; ++s) {
+        spike_handle h = hs[v[b0 + s]];
+        ba.kp[s] = reinterpret_cast<const spike::KParams*>(h->ws + h->plan.off_kp);
+        p[s] = h->plan.p;
+        lo[s] = &h->cfg.level_off;
+      }
+      const spike_handle h0 = hs[v[b0]];
+      if (int e = spike::launch_factor_batch(ba, p.data(), lo, h0->cfg, h0->plan.kl, h0->plan.ku, stream))
+        return fail(e);
+    }
+  }
+  for (int i : rest) {
+    spike_handle h = hs[i];
+    int e = spike::launch_init_status(h->kp.status, stream);
+    if (!e && h->kp.sweeps) e = spike::run_zero_counters(h->kp.sweeps, spike::kSweepCounters, stream);
+    if (!e && h->plan.n > 0) e = spike::launch_factor(h->kp, h->cfg, stream);
+    if (e) return fail(e);
+  }
+  for (int i = 0; i < count; ++i) {
+    spike_handle h = hs[i];
+    if (h->plan.n > 0 && h->plan.refine_enabled())
+      if (int e = spike::prepare_refine(h->kp, h->plan, h->ws, stream)) return fail(e);
+  }
+  for (int i = 0; i < count; ++i) out[i] = hs[i];
+  return 0;
+}
+
 int spike_solve(spike_handle h, int32_t nrhs, double* dB, int64_t ldb, hipStream_t stream) {
   return solve_common(h, nrhs, dB, ldb, stream, false);
 }

@@ -1,5 +1,7 @@
 // Stage sequencing: dispatch on the panel widths and precision chosen by the
 // planner, and order the leaf and merge launches of each stage.
+#include <algorithm>
+
 #include "spike_launch.hpp"
 
 namespace spike {
@@ -130,6 +132,66 @@ int launch_mlevel_batch(const BatchArgs& ba, int mht, hipStream_t st, int nitems
     case 10: return run_msolve_level_batch<10>(ba, st, nitems, trans, up);
     default: return run_msolve_level_batch<16>(ba, st, nitems, trans, up);
   }
+}
+
+// The factor stage of up to kMaxBatch systems with one kernel configuration
+// (the MFMA block LU, the tile-engine tips and the reduced system on MFMA
+// tiles, equal bandwidths, non-pivoting): every kernel launch covers all of
+// them.  p[s] is system s's partition count, level_off[s] its merge levels.
+int launch_factor_batch(const BatchArgs& ba0, const int* p, const std::vector<const std::vector<int>*>& level_off,
+                        const LaunchCfg& c, int kl, int ku, hipStream_t st) {
+  BatchArgs ba = ba0;
+  const int ns = ba.nsys;
+  int e;
+  if ((e = run_init_status_batch(ba, st))) return e;
+  std::vector<int> cnt(ns), mids(ns);
+  int maxL = 0;
+  for (int s = 0; s < ns; ++s) {
+    cnt[s] = p[s];
+    mids[s] = p[s] >= 3 ? p[s] - 2 : 0;   // middle partitions: tile-engine tips (fast_tips)
+    maxL = std::max(maxL, (int)level_off[s]->size() - 1);
+  }
+  const bool f32 = c.fp32;
+  switch (c.ht) {
+#define SPIKE_FB(H)                                                                                       \
+  case H:                                                                                               \
+    if ((e = f32 ? run_flu_batch<float, H>(ba, cnt.data(), st) : run_flu_batch<double, H>(ba, cnt.data(), st))) \
+      return e;                                                                                         \
+    for (int s = 0; s < ns; ++s) cnt[s] = p[s] > 1 ? p[s] : 0;                                           \
+    for (int which = 0; which < 3; ++which) {                                                           \
+      const int* cc = which == 0 ? cnt.data() : mids.data();                                            \
+      if ((e = f32 ? run_ftip_batch<float, H>(ba, cc, which, kl, ku, c.fast_lds, st)                     \
+                   : run_ftip_batch<double, H>(ba, cc, which, kl, ku, c.fast_lds, st)))                  \
+        return e;                                                                                       \
+    }                                                                                                   \
+    break;
+    SPIKE_FB(1)
+    SPIKE_FB(2)
+    SPIKE_FB(4)
+    SPIKE_FB(8)
+    SPIKE_FB(10)
+#undef SPIKE_FB
+    default:
+      return -1;
+  }
+  for (int l = 0; l < maxL; ++l) {
+    for (int s = 0; s < ns; ++s) {
+      const std::vector<int>& lo = *level_off[s];
+      const int L = (int)lo.size() - 1;
+      ba.mbeg[s] = l < L ? lo[l] : 0;
+      cnt[s] = l < L ? lo[l + 1] - lo[l] : 0;
+    }
+    switch (c.mht) {
+      case 1: e = run_mfactor_level_batch<1>(ba, cnt.data(), kl, ku, st); break;
+      case 2: e = run_mfactor_level_batch<2>(ba, cnt.data(), kl, ku, st); break;
+      case 4: e = run_mfactor_level_batch<4>(ba, cnt.data(), kl, ku, st); break;
+      case 8: e = run_mfactor_level_batch<8>(ba, cnt.data(), kl, ku, st); break;
+      case 10: e = run_mfactor_level_batch<10>(ba, cnt.data(), kl, ku, st); break;
+      default: e = run_mfactor_level_batch<16>(ba, cnt.data(), kl, ku, st); break;
+    }
+    if (e) return e;
+  }
+  return 0;
 }
 
 int launch_factor(const KParams& k0, const LaunchCfg& c, hipStream_t st) {

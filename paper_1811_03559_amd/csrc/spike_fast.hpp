@@ -86,10 +86,10 @@ __global__ __launch_bounds__(NT) void k_diag_inv(KParams k) {
 // U^{-1} L^{-1}[0; B'], from the trailing block of U from the 16-aligned row
 // ju <= m - klf.
 template <typename T, int HT>
-__global__ __launch_bounds__(NT) void k_ftip_v(KParams k, int ncg) {
+__device__ __forceinline__ void ftip_v_body(const KParams& k, const int bx_, const int gx_, int ncg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int b = xcd_grouped(blockIdx.x, gridDim.x);
+  const int b = xcd_grouped(bx_, gx_);
   const int li = b / ncg, cg = b % ncg;
   const LeafDesc L = k.leaves[li];
   if (L.type == LEAF_SINGLE) return;
@@ -137,12 +137,23 @@ __global__ __launch_bounds__(NT) void k_ftip_v(KParams k, int ncg) {
   tile_sweep<T, HT, OP_U_BWD>(Au, dv + (int64_t)(ju / 16) * dinv_stride(), su, du, 64 * cg, kuf, lds);
   if (cg == 0) note_sweep(k, 0, L.type, Au.m, m);
 }
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_v(KParams k, int ncg) {
+  ftip_v_body<T, HT>(k, blockIdx.x, gridDim.x, ncg);
+}
+// the same for up to kMaxBatch systems: workgroup i belongs to system s
+// with off[s] <= i < off[s + 1] (its parameter block at kp[s])
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_v_b(BatchArgs ba, int ncg) {
+  const int s = batch_sys(ba, blockIdx.x);
+  ftip_v_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.off[s + 1] - ba.off[s], ncg);
+}
 
 template <typename T, int HT>
-__global__ __launch_bounds__(NT) void k_ftip_w(KParams k, int ncg) {
+__device__ __forceinline__ void ftip_w_body(const KParams& k, const int bx_, const int gx_, int ncg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int b = xcd_grouped(blockIdx.x, gridDim.x);
+  const int b = xcd_grouped(bx_, gx_);
   const int li = 1 + b / ncg, cg = b % ncg;
   const LeafDesc L = k.leaves[li];
   BandAcc<T> A = leaf_band<T>(k, L);
@@ -155,12 +166,23 @@ __global__ __launch_bounds__(NT) void k_ftip_w(KParams k, int ncg) {
   tile_sweep<T, HT, OP_L_FWD>(A, dv, src, dst, 64 * cg, kl, lds);
   if (cg == 0) note_sweep(k, 0, L.type, A.m, m);   // W: L sweep
 }
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_w(KParams k, int ncg) {
+  ftip_w_body<T, HT>(k, blockIdx.x, gridDim.x, ncg);
+}
+// the same for up to kMaxBatch systems: workgroup i belongs to system s
+// with off[s] <= i < off[s + 1] (its parameter block at kp[s])
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_w_b(BatchArgs ba, int ncg) {
+  const int s = batch_sys(ba, blockIdx.x);
+  ftip_w_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.off[s + 1] - ba.off[s], ncg);
+}
 
 template <typename T, int HT>
-__global__ __launch_bounds__(NT) void k_ftip_u(KParams k, int ncg) {
+__device__ __forceinline__ void ftip_u_body(const KParams& k, const int bx_, const int gx_, int ncg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int b = xcd_grouped(blockIdx.x, gridDim.x);
+  const int b = xcd_grouped(bx_, gx_);
   const int li = 1 + b / ncg, cg = b % ncg;
   const LeafDesc L = k.leaves[li];
   BandAcc<T> A = leaf_band<T>(k, L);
@@ -173,6 +195,17 @@ __global__ __launch_bounds__(NT) void k_ftip_u(KParams k, int ncg) {
   TDst dst = tdst(tp, tp + ku, 1, 1, kw, ku, m - kl, m);
   tile_sweep<T, HT, OP_U_BWD>(A, dv, src, dst, 64 * cg, kw, lds);
   if (cg == 0) note_sweep(k, 0, L.type, A.m, m, 2);   // V and W: one U pass
+}
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_u(KParams k, int ncg) {
+  ftip_u_body<T, HT>(k, blockIdx.x, gridDim.x, ncg);
+}
+// the same for up to kMaxBatch systems: workgroup i belongs to system s
+// with off[s] <= i < off[s + 1] (its parameter block at kp[s])
+template <typename T, int HT>
+__global__ __launch_bounds__(NT) void k_ftip_u_b(BatchArgs ba, int ncg) {
+  const int s = batch_sys(ba, blockIdx.x);
+  ftip_u_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.off[s + 1] - ba.off[s], ncg);
 }
 
 // ---------------------------------------------------------------- solve stage
@@ -491,6 +524,44 @@ int run_fast_phase(const KParams& k, const LaunchCfg& c, hipStream_t st, double*
       allow_lds_f(k_fdtstage<T, HT>, c.fast_lds);
       ProfScope ps("k_fdtstage", st);
       hipLaunchKernelGGL((k_fdtstage<T, HT>), dim3(k.p), dim3(NT), c.fast_lds, st, k, B, ldb, nrhs);
+      break;
+    }
+  }
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
+// the tip kernels for several systems (which: 0 V tips of every partition,
+// 1 W L-sweep and 2 [V W] U-sweep of the middle partitions); cnt[s] counts
+// the system's partitions for which the kernel runs
+template <typename T, int HT>
+int run_ftip_batch(BatchArgs ba, const int* cnt, int which, int kl, int ku, size_t lds, hipStream_t st) {
+  const int kmax = kl > ku ? kl : ku;
+  const int ncg = which == 0 ? (kmax + 63) / 64 : (which == 1 ? (kl + 63) / 64 : (kl + ku + 63) / 64);
+  int tot = 0;
+  for (int s = 0; s < ba.nsys; ++s) {
+    ba.off[s] = tot;
+    tot += cnt[s] * ncg;
+  }
+  ba.off[ba.nsys] = tot;
+  if (tot <= 0) return 0;
+  switch (which) {
+    case 0: {
+      allow_lds_f(k_ftip_v_b<T, HT>, lds);
+      ProfScope ps("k_ftip_v", st);
+      hipLaunchKernelGGL((k_ftip_v_b<T, HT>), dim3(tot), dim3(NT), lds, st, ba, ncg);
+      break;
+    }
+    case 1: {
+      allow_lds_f(k_ftip_w_b<T, HT>, lds);
+      ProfScope ps("k_ftip_w", st);
+      hipLaunchKernelGGL((k_ftip_w_b<T, HT>), dim3(tot), dim3(NT), lds, st, ba, ncg);
+      break;
+    }
+    default: {
+      allow_lds_f(k_ftip_u_b<T, HT>, lds);
+      ProfScope ps("k_ftip_u", st);
+      hipLaunchKernelGGL((k_ftip_u_b<T, HT>), dim3(tot), dim3(NT), lds, st, ba, ncg);
       break;
     }
   }

@@ -319,11 +319,11 @@ constexpr size_t flu_lds_bytes() {
 }
 
 template <typename T, int HT>
-__global__ __launch_bounds__(flu_nw<HT>() * 64) void k_flu(KParams k) {
+__device__ __forceinline__ void flu_kernel_body(const KParams& k, const int bx_, const int gx_) {
   constexpr int NW = flu_nw<HT>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int li = blockIdx.x;
+  const int li = bx_;
   const LeafDesc L = k.leaves[li];
   const int m = L.m;
   const BandAcc<T> A = leaf_band<T>(k, L);
@@ -361,6 +361,41 @@ __global__ __launch_bounds__(flu_nw<HT>() * 64) void k_flu(KParams k) {
   }
   if (L.type == LEAF_LAST) flu_body<T, HT, true>(k, L, lds);
   else flu_body<T, HT, false>(k, L, lds);
+}
+template <typename T, int HT>
+__global__ __launch_bounds__(flu_nw<HT>() * 64) void k_flu(KParams k) {
+  flu_kernel_body<T, HT>(k, blockIdx.x, gridDim.x);
+}
+// the same for up to kMaxBatch systems: workgroup i belongs to system s
+// with off[s] <= i < off[s + 1] (its parameter block at kp[s])
+template <typename T, int HT>
+__global__ __launch_bounds__(flu_nw<HT>() * 64) void k_flu_b(BatchArgs ba) {
+  const int s = batch_sys(ba, blockIdx.x);
+  flu_kernel_body<T, HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.off[s + 1] - ba.off[s]);
+}
+
+// fills ba.off from the per-system counts
+inline int batch_prefix(BatchArgs& ba, const int* cnt, int mult) {
+  int tot = 0;
+  for (int s = 0; s < ba.nsys; ++s) {
+    ba.off[s] = tot;
+    tot += cnt[s] * mult;
+  }
+  ba.off[ba.nsys] = tot;
+  return tot;
+}
+
+template <typename T, int HT>
+int run_flu_batch(BatchArgs ba, const int* cnt, hipStream_t st) {
+  constexpr int NW = flu_nw<HT>();
+  const size_t lds = flu_lds_bytes<T, HT>();
+  const int n = batch_prefix(ba, cnt, 1);
+  if (n <= 0) return 0;
+  hipFuncSetAttribute((const void*)k_flu_b<T, HT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  ProfScope ps("k_flu", st);
+  hipLaunchKernelGGL((k_flu_b<T, HT>), dim3(n), dim3(NW * 64), lds, st, ba);
+  SPIKE_CHECK_LAUNCH();
+  return 0;
 }
 
 template <typename T, int HT>

@@ -23,13 +23,29 @@ template int run_flu<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStr
 template int run_fast_phase<SPIKE_T, SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, double*, int64_t,
                                                 int, int);
 template int run_fast_phase_batch<SPIKE_T, SPIKE_HT>(const BatchArgs&, size_t, hipStream_t, int, int);
+template int run_ftip_batch<SPIKE_T, SPIKE_HT>(BatchArgs, const int*, int, int, int, size_t, hipStream_t);
+#if SPIKE_HT <= 10
+template int run_flu_batch<SPIKE_T, SPIKE_HT>(BatchArgs, const int*, hipStream_t);
+#endif
 #elif defined(SPIKE_INST_MFAST)
 template int run_mfactor<SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t);
 template int run_msolve<SPIKE_HT>(const KParams&, const LaunchCfg&, hipStream_t, int, bool);
 template int run_msolve_level_batch<SPIKE_HT>(const BatchArgs&, hipStream_t, int, bool, bool);
+template int run_mfactor_level_batch<SPIKE_HT>(BatchArgs, const int*, int, int, hipStream_t);
 #elif defined(SPIKE_INST_COMMON)
 int run_init_status(DevStatus* s, hipStream_t st) {
   hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, s);
+  SPIKE_CHECK_LAUNCH();
+  return 0;
+}
+
+static __global__ void k_init_status_b(BatchArgs ba) {
+  if (threadIdx.x == 0 && blockIdx.x < (unsigned)ba.nsys) init_status_fields(ba.kp[blockIdx.x]->status);
+}
+
+int run_init_status_batch(const BatchArgs& ba, hipStream_t st) {
+  if (ba.nsys <= 0) return 0;
+  hipLaunchKernelGGL(k_init_status_b, dim3(ba.nsys), dim3(64), 0, st, ba);
   SPIKE_CHECK_LAUNCH();
   return 0;
 }

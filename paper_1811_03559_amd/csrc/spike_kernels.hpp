@@ -60,19 +60,21 @@ static __global__ void k_zero_counters(unsigned long long* c, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
 }
 
+__device__ inline void init_status_fields(DevStatus* s) {
+  s->zero_row = ULLONG_MAX;
+  s->iface = ULLONG_MAX;
+  s->n_boosts = 0;
+  s->refine_iters = 0;
+  s->min_pivot_bits = dbits(__builtin_huge_val());
+  s->berr = -1.0;
+  s->refine_active = 0;
+  s->skip = 1;
+  s->anorm_inf_bits = 0ull;
+  s->anorm_one_bits = 0ull;
+}
+
 static __global__ void k_init_status(DevStatus* s) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    s->zero_row = ULLONG_MAX;
-    s->iface = ULLONG_MAX;
-    s->n_boosts = 0;
-    s->refine_iters = 0;
-    s->min_pivot_bits = dbits(__builtin_huge_val());
-    s->berr = -1.0;
-    s->refine_active = 0;
-    s->skip = 1;
-    s->anorm_inf_bits = 0ull;
-    s->anorm_one_bits = 0ull;
-  }
+  if (threadIdx.x == 0 && blockIdx.x == 0) init_status_fields(s);
 }
 
 template <typename T>

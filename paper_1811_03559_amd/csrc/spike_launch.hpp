@@ -110,6 +110,16 @@ int run_fast_phase_batch(const BatchArgs& ba, size_t lds, hipStream_t st, int ph
 template <int HT>
 int run_msolve_level_batch(const BatchArgs& ba, hipStream_t st, int nitems, bool trans, bool up);
 int run_gform_batch(const BatchArgs& ba, hipStream_t st, int nitems);
+// Factor-stage launches for several systems of one kernel configuration;
+// cnt[s] counts system s's work units (partitions, or merges of the level at
+// ba.mbeg[s]); the runners fill ba.off from it.
+int run_init_status_batch(const BatchArgs& ba, hipStream_t st);
+template <typename T, int HT>
+int run_flu_batch(BatchArgs ba, const int* cnt, hipStream_t st);
+template <typename T, int HT>
+int run_ftip_batch(BatchArgs ba, const int* cnt, int which, int kl, int ku, size_t lds, hipStream_t st);
+template <int HT>
+int run_mfactor_level_batch(BatchArgs ba, const int* cnt, int kl, int ku, hipStream_t st);
 template <typename T, int HT>
 int run_flu(const KParams& k, const LaunchCfg& c, hipStream_t st);
 template <typename T, int HT>
@@ -136,6 +146,8 @@ int run_zero_counters(unsigned long long* c, int n, hipStream_t st);
 int launch_phase_batch(const BatchArgs& ba, bool fp32, int ht, size_t lds, hipStream_t st, int phase, int nitems);
 int launch_mlevel_batch(const BatchArgs& ba, int mht, hipStream_t st, int nitems, bool trans, bool up);
 int launch_factor(const KParams& k, const LaunchCfg& c, hipStream_t st);
+int launch_factor_batch(const BatchArgs& ba, const int* p, const std::vector<const std::vector<int>*>& level_off,
+                        const LaunchCfg& c, int kl, int ku, hipStream_t st);
 int launch_solve(const KParams& k, const LaunchCfg& c, hipStream_t st, double* B, int64_t ldb, int nrhs,
                  bool trans);
 

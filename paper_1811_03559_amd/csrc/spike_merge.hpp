@@ -129,12 +129,12 @@ __device__ inline FJob fused_job(const KParams& k, const MergeDesc& J, int ph, i
 // buffered LDS, the next chunk loaded into registers during the current one.
 constexpr int FG_T = 64, FG_KC = 16, FG_PAD = FG_T + 1;
 template <int PH>
-__global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj, int tn) {
+__device__ __forceinline__ void mgemm_body(const KParams& k, const int bx_, const int gx_, int mbeg, int tpj, int tn) {
   using M = Mf<double>;
   __shared__ double As[2][FG_KC * FG_PAD];   // As[kk][i]
   __shared__ double Bs[2][FG_KC * FG_PAD];   // Bs[kk][j]
   constexpr int NJ = fjobs(PH);
-  const int b = xcd_grouped(blockIdx.x, gridDim.x);
+  const int b = xcd_grouped(bx_, gx_);
   const int tile = b % tpj, rest = b / tpj;
   const int job = rest % NJ, mm = rest / NJ;
   const MergeDesc J = k.merges[mbeg + mm];
@@ -213,6 +213,17 @@ __global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj, int 
         if (g.addI && lo && i == jj) v += 1.0;
         (lo ? g.c_lo : g.c_hi)[i + (int64_t)jj * g.ldc] = v;
       }
+}
+template <int PH>
+__global__ __launch_bounds__(NT) void k_mgemm(KParams k, int mbeg, int tpj, int tn) {
+  mgemm_body<PH>(k, blockIdx.x, gridDim.x, mbeg, tpj, tn);
+}
+// the same for up to kMaxBatch systems: workgroup i belongs to system s
+// with off[s] <= i < off[s + 1] (its parameter block at kp[s])
+template <int PH>
+__global__ __launch_bounds__(NT) void k_mgemm_b(BatchArgs ba, int tpj, int tn) {
+  const int s = batch_sys(ba, blockIdx.x);
+  mgemm_body<PH>(*ba.kp[s], blockIdx.x - ba.off[s], ba.off[s + 1] - ba.off[s], ba.mbeg[s], tpj, tn);
 }
 
 // ---------------------------------------------------------------- LU of S
@@ -620,7 +631,7 @@ __host__ __device__ constexpr size_t mlu_blk_lds_bytes() {
 }
 
 template <int NBT>
-__global__ __launch_bounds__(64 * (NBT + 1)) void k_mlu_blk(KParams k, int mbeg) {
+__device__ __forceinline__ void mlu_blk_body(const KParams& k, const int bx_, const int gx_, int mbeg) {
   using Mq = Mf<double>;
   using v4 = Mq::v4;
   constexpr int NMAX = 16 * NBT, PW = MLB_PW, TS = 16 * PW, BUF = NMAX * PW;
@@ -637,7 +648,7 @@ __global__ __launch_bounds__(64 * (NBT + 1)) void k_mlu_blk(KParams k, int mbeg)
   int* tlive = pvt + 32;                               // [2][NBT] tile has a row open before the block
   int* zflag = tlive + 2 * NBT;
 
-  const MergeDesc Jm = k.merges[mbeg + blockIdx.x];
+  const MergeDesc Jm = k.merges[mbeg + bx_];
   const int n = k.ku, mi = Jm.mif;
   const int nbk = (n + 15) / 16;
   double* S = k.sfac + (int64_t)mi * n * n;
@@ -956,6 +967,17 @@ __global__ __launch_bounds__(64 * (NBT + 1)) void k_mlu_blk(KParams k, int mbeg)
   for (int r = tid; r < n; r += blockDim.x) perm[rstep[r]] = r;
   if (tid == 0 && *zflag) atomicMin(&k.status->iface, (unsigned long long)(mi + 1));
 }
+template <int NBT>
+__global__ __launch_bounds__(64 * (NBT + 1)) void k_mlu_blk(KParams k, int mbeg) {
+  mlu_blk_body<NBT>(k, blockIdx.x, gridDim.x, mbeg);
+}
+// the same for up to kMaxBatch systems: workgroup i belongs to system s
+// with off[s] <= i < off[s + 1] (its parameter block at kp[s])
+template <int NBT>
+__global__ __launch_bounds__(64 * (NBT + 1)) void k_mlu_blk_b(BatchArgs ba) {
+  const int s = batch_sys(ba, blockIdx.x);
+  mlu_blk_body<NBT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.off[s + 1] - ba.off[s], ba.mbeg[s]);
+}
 
 // ------------------------------------------------------- beta, delta solves
 // LDS doubles of k_mtrsm<HT>.
@@ -967,10 +989,10 @@ __host__ __device__ constexpr int mtrsm_lds_elems() {
 // logical workgroup (merge * 2 + job) * ncg + cg; job 0: beta = S^{-1} V_t(R),
 // job 1: delta = S^{-1} Dm; columns [64 cg, 64 cg + 64).
 template <int HT>
-__global__ __launch_bounds__(NT) void k_mtrsm(KParams k, int mbeg, int ncg) {
+__device__ __forceinline__ void mtrsm_body(const KParams& k, const int bx_, const int gx_, int mbeg, int ncg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lds = reinterpret_cast<double*>(smem_raw);
-  const int b = xcd_grouped(blockIdx.x, gridDim.x);
+  const int b = xcd_grouped(bx_, gx_);
   const int cg = b % ncg, rest = b / ncg;
   const int job = rest % 2, mm = rest / 2;
   const MergeDesc J = k.merges[mbeg + mm];
@@ -997,6 +1019,17 @@ __global__ __launch_bounds__(NT) void k_mtrsm(KParams k, int mbeg, int ncg) {
   const TDst d = tdst(X, nullptr, 1, 1, kw, ku, ku, ku);
   tile_sweep<double, HT, OP_L_FWD>(D, dv, s, d, c0, ncol, lds);
   tile_sweep<double, HT, OP_U_BWD>(D, dv, s, d, c0, ncol, lds);
+}
+template <int HT>
+__global__ __launch_bounds__(NT) void k_mtrsm(KParams k, int mbeg, int ncg) {
+  mtrsm_body<HT>(k, blockIdx.x, gridDim.x, mbeg, ncg);
+}
+// the same for up to kMaxBatch systems: workgroup i belongs to system s
+// with off[s] <= i < off[s + 1] (its parameter block at kp[s])
+template <int HT>
+__global__ __launch_bounds__(NT) void k_mtrsm_b(BatchArgs ba, int ncg) {
+  const int s = batch_sys(ba, blockIdx.x);
+  mtrsm_body<HT>(*ba.kp[s], blockIdx.x - ba.off[s], ba.off[s + 1] - ba.off[s], ba.mbeg[s], ncg);
 }
 
 // ---------------------------------------------------------------- solves
@@ -1326,6 +1359,65 @@ __global__ __launch_bounds__(NT) void k_msolve_b(BatchArgs ba) {
 template <typename K>
 inline void allow_lds_m(K kernel, size_t lds) {
   (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// One level of the reduced-system factorisation for several systems of the
+// same bandwidths (orders up to 160: the blocked LU); cnt[s] merges of
+// system s from ba.mbeg[s] on.
+template <int HT>
+int run_mfactor_level_batch(BatchArgs ba, const int* cnt, int kl, int ku, hipStream_t st) {
+  const int kmax = kl > ku ? kl : ku, kw = kl + ku;
+  const size_t tr_lds = (size_t)mtrsm_lds_elems<HT>() * 8 + 2048;
+  const int ncg = (kmax + 63) / 64;
+  const int ftn = (kw + FG_T - 1) / FG_T, ftiles = ((kmax + FG_T - 1) / FG_T) * ftn;
+  auto prefix = [&](int mult) {
+    int tot = 0;
+    for (int s = 0; s < ba.nsys; ++s) {
+      ba.off[s] = tot;
+      tot += cnt[s] * mult;
+    }
+    ba.off[ba.nsys] = tot;
+    return tot;
+  };
+  if (prefix(1) <= 0) return 0;
+  {
+    ProfScope ps("k_mgemm", st);
+    hipLaunchKernelGGL((k_mgemm_b<1>), dim3(prefix(fjobs(1) * ftiles)), dim3(NT), 0, st, ba, ftiles, ftn);
+    SPIKE_CHECK_LAUNCH();
+  }
+  {
+    ProfScope ps("k_mlu", st);
+    const int nw = (ku + 15) / 16 + 1;
+    const int nl = prefix(1);
+    if (ku <= 64) {
+      allow_lds_m(k_mlu_blk_b<4>, mlu_blk_lds_bytes<4>());
+      hipLaunchKernelGGL((k_mlu_blk_b<4>), dim3(nl), dim3(64 * nw), mlu_blk_lds_bytes<4>(), st, ba);
+    } else if (ku <= 128) {
+      allow_lds_m(k_mlu_blk_b<8>, mlu_blk_lds_bytes<8>());
+      hipLaunchKernelGGL((k_mlu_blk_b<8>), dim3(nl), dim3(64 * nw), mlu_blk_lds_bytes<8>(), st, ba);
+    } else {
+      allow_lds_m(k_mlu_blk_b<10>, mlu_blk_lds_bytes<10>());
+      hipLaunchKernelGGL((k_mlu_blk_b<10>), dim3(nl), dim3(64 * nw), mlu_blk_lds_bytes<10>(), st, ba);
+    }
+    SPIKE_CHECK_LAUNCH();
+  }
+  {
+    allow_lds_m(k_mtrsm_b<HT>, tr_lds);
+    ProfScope ps("k_mtrsm", st);
+    hipLaunchKernelGGL((k_mtrsm_b<HT>), dim3(prefix(2 * ncg)), dim3(NT), tr_lds, st, ba, ncg);
+    SPIKE_CHECK_LAUNCH();
+  }
+  {
+    ProfScope ps("k_mgemm", st);
+    hipLaunchKernelGGL((k_mgemm_b<45>), dim3(prefix(fjobs(45) * ftiles)), dim3(NT), 0, st, ba, ftiles, ftn);
+    SPIKE_CHECK_LAUNCH();
+  }
+  {
+    ProfScope ps("k_mgemm", st);
+    hipLaunchKernelGGL((k_mgemm_b<6>), dim3(prefix(fjobs(6) * ftiles)), dim3(NT), 0, st, ba, ftiles, ftn);
+    SPIKE_CHECK_LAUNCH();
+  }
+  return 0;
 }
 
 template <int HT>

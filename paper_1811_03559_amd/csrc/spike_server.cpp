@@ -96,6 +96,7 @@ struct Resident {
   uint64_t last_use = 0;
   bool info_known = false;     // numerical status read once, after the factorisation
   int64_t info = 0;
+  const spike_request* freq = nullptr;   // its factorisation waits for this pass's batch
 };
 
 struct Req {
@@ -124,6 +125,7 @@ struct spike_server_s {
   std::vector<Req*> inflight;
   std::unordered_map<int64_t, Req*> reqs;
   std::unordered_map<int64_t, Resident*> res;
+  std::map<int, std::vector<Resident*>> deferred;   // new factorisations of a pass, per stream
   std::vector<hipEvent_t> event_pool;
   std::vector<double> lat;
   int64_t next_ticket = 1;
@@ -205,19 +207,60 @@ struct spike_server_s {
     r->bytes = need;
     r->stream = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     r->last = take_event();
-    e = spike_factor(q->r.n, q->r.kl, q->r.ku, q->r.dAB, q->r.ldab, &q->r.opts, base + off, need,
-                     streams[r->stream], &r->h);
-    if (e) {
-      pool->release(off, need);
-      if (r->last) event_pool.push_back(r->last);
-      delete r;
-      *err = e;
-      return nullptr;
-    }
-    (void)hipEventRecord(r->last, streams[r->stream]);
+    // factored with the other new matrices of this pass (flush_factors)
+    r->freq = &q->r;
+    deferred[r->stream].push_back(r);
     res[r->id] = r;
-    ++factorizations;
     return r;
+  }
+
+  // The factorisations admitted in this pass, one spike_factor_batch per
+  // home stream (before the stream's solves); a resident whose factorisation
+  // fails is dropped and its id's error returned through failed_ids.
+  void flush_factors(std::map<int64_t, int>& failed_ids) {
+    for (auto& kv : deferred) {
+      std::vector<Resident*>& v = kv.second;
+      if (v.empty()) continue;
+      const hipStream_t st = streams[kv.first];
+      const int cnt = (int)v.size();
+      std::vector<int64_t> n(cnt), ld(cnt);
+      std::vector<int32_t> kl(cnt), ku(cnt);
+      std::vector<const double*> ab(cnt);
+      std::vector<spike_opts> op(cnt);
+      std::vector<void*> wk(cnt);
+      std::vector<size_t> wb(cnt);
+      std::vector<spike_handle> hs(cnt, nullptr);
+      for (int i = 0; i < cnt; ++i) {
+        const spike_request& q = *v[i]->freq;
+        n[i] = q.n;
+        kl[i] = q.kl;
+        ku[i] = q.ku;
+        ab[i] = q.dAB;
+        ld[i] = q.ldab;
+        op[i] = q.opts;
+        wk[i] = base + v[i]->off;
+        wb[i] = v[i]->bytes;
+      }
+      int e = spike_factor_batch(cnt, n.data(), kl.data(), ku.data(), ab.data(), ld.data(), op.data(), wk.data(),
+                                 wb.data(), st, hs.data());
+      for (int i = 0; i < cnt; ++i) {
+        Resident* r = v[i];
+        int ei = e;
+        if (e) {   // find the failing system: factor the others one by one
+          const spike_request& q = *r->freq;
+          ei = spike_factor(q.n, q.kl, q.ku, q.dAB, q.ldab, &q.opts, base + r->off, r->bytes, st, &hs[i]);
+        }
+        r->freq = nullptr;
+        if (ei) {
+          failed_ids[r->id] = ei;
+          continue;
+        }
+        r->h = hs[i];
+        (void)hipEventRecord(r->last, st);
+        ++factorizations;
+      }
+      v.clear();
+    }
   }
 
   void finish(Req* q, int state, int err) {
@@ -289,8 +332,36 @@ struct spike_server_s {
       --slots;
       did = true;
     }
+    std::map<int64_t, int> failed_ids;
+    flush_factors(failed_ids);
+    if (!failed_ids.empty()) {
+      for (auto& kv : batch) {
+        std::vector<Req*>& v = kv.second;
+        for (size_t i = 0; i < v.size();) {
+          auto f = failed_ids.find(v[i]->r.matrix_id);
+          if (f == failed_ids.end()) {
+            ++i;
+            continue;
+          }
+          Req* q = v[i];
+          finish(q, 3, f->second);
+          load[q->res->stream]--;
+          q->res = nullptr;
+          v[i] = v.back();
+          v.pop_back();
+        }
+      }
+      for (auto& kv : failed_ids) {
+        auto it = res.find(kv.first);
+        if (it != res.end()) {
+          it->second->pending = 0;
+          drop(it->second);
+        }
+      }
+    }
     for (auto& kv : batch) {
       std::vector<Req*>& v = kv.second;
+      if (v.empty()) continue;
       const hipStream_t st = streams[kv.first];
       std::vector<spike_handle> hs;
       std::vector<int32_t> nr, tr;

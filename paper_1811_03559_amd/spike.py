@@ -126,6 +126,8 @@ def lib():
             L.spike_handle_plan.argtypes = [_c_p, ctypes.POINTER(PlanInfo)]
             L.spike_destroy.restype = ctypes.c_int
             L.spike_destroy.argtypes = [_c_p]
+            L.spike_factor_batch.restype = ctypes.c_int
+            L.spike_factor_batch.argtypes = [_c_i32, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
             L.spike_solve_batch.restype = ctypes.c_int
             L.spike_solve_batch.argtypes = [_c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, _c_p]
             L.spike_graph_capture_batch.restype = ctypes.c_int
@@ -545,6 +547,42 @@ def _batch_arrays(facs, Bs, trans):
         bp[i] = B.data_ptr()
         ld[i] = B.stride(0) if B.shape[0] > 1 else max(f.n, 1)
     return cnt, hs, nr, bp, ld, tr
+
+
+def factor_batch(systems, stream=None, **opts):
+    """Factor several banded systems with batched launches
+    (spike_factor_batch).  ``systems``: a list of (ab, kl, ku) with ab a
+    float64 CUDA band tensor; ``opts`` apply to every system.  Returns one
+    Factorization per system, each with its own workspace."""
+    import torch
+    cnt = len(systems)
+    facs = []
+    for ab, kl, ku in systems:
+        _check_band(ab, kl, ku)
+        f = Factorization.__new__(Factorization)
+        f.n, f.ldab = int(ab.shape[0]), int(ab.shape[1])
+        f.kl, f.ku = int(kl), int(ku)
+        f.opts = make_opts(**opts)
+        f.nrhs_max = f.opts.nrhs_max
+        f.ab, f.device = ab, ab.device
+        f.ws = torch.empty(max(workspace_size(f.n, kl, ku, **opts), 256), dtype=torch.uint8, device=ab.device)
+        f.h = None
+        facs.append(f)
+    n = (_c_i64 * cnt)(*[f.n for f in facs])
+    kl = (_c_i32 * cnt)(*[f.kl for f in facs])
+    ku = (_c_i32 * cnt)(*[f.ku for f in facs])
+    ap = (_c_p * cnt)(*[f.ab.data_ptr() for f in facs])
+    ld = (_c_i64 * cnt)(*[f.ldab for f in facs])
+    op = (Opts * cnt)(*[f.opts for f in facs])
+    wp = (_c_p * cnt)(*[f.ws.data_ptr() for f in facs])
+    wb = (_c_size * cnt)(*[f.ws.numel() for f in facs])
+    hs = (_c_p * cnt)()
+    rc = lib().spike_factor_batch(cnt, n, kl, ku, ap, ld, op, wp, wb, _stream_handle(stream), hs)
+    if rc != 0:
+        raise SpikeError("spike_factor_batch", rc)
+    for f, h in zip(facs, hs):
+        f.h = ctypes.c_void_p(h)
+    return facs
 
 
 def solve_batch(facs, Bs, trans=False, stream=None):

@@ -393,3 +393,25 @@ def test_profile_only_name_length():
     assert spike.lib().spike_profile_only(b"x" * 48) == -1
     spike.profile_only("k_flu")
     spike.profile_only(None)
+
+
+def test_factor_batch_argument_errors():
+    """spike_factor_batch checks every system before anything is launched."""
+    import ctypes
+    L = spike.lib()
+    I64, I32, P, SZ = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+    out = (P * 2)()
+
+    def call(count, n=(1000, 2000), kl=(4, 4), ku=(4, 4), ldab=(9, 9), wb=(1 << 40, 1 << 40),
+             dab=(256, 256), dw=(256, 512)):
+        return L.spike_factor_batch(count, (I64 * 2)(*n), (I32 * 2)(*kl), (I32 * 2)(*ku), (P * 2)(*dab),
+                                    (I64 * 2)(*ldab), None, (P * 2)(*dw), (SZ * 2)(*wb), None, out)
+    assert L.spike_factor_batch(-1, None, None, None, None, None, None, None, None, None, None) == -11
+    assert L.spike_factor_batch(0, None, None, None, None, None, None, None, None, None, None) == 0
+    assert L.spike_factor_batch(2, None, None, None, None, None, None, None, None, None, None) == -12
+    assert call(2, n=(1000, -5)) == -1
+    assert call(2, kl=(4, -1)) == -2
+    assert call(2, ldab=(9, 8)) == -5
+    assert call(2, dw=(256, 100)) == -7
+    assert call(2, wb=(1 << 40, 16)) == -8
+    assert call(2, dab=(256, 0)) == -4
