@@ -43,56 +43,76 @@ struct PivStats {
   int first_zero;
 };
 
-// LU (no interchanges) of one 16 x 16 tile held by one wavefront in the
-// accumulator layout, with the inverses of its unit-lower and upper factors.
-// a: in A, out L\U; xl: L^{-1}; xu: U^{-1} (same layout).  Rows at or beyond
-// `mrem` are padding (identity) and are left out of the statistics.  Pivot
-// rows and columns move between lanes by cross-lane shuffles.
+// The diagonal tile of a panel is factored in a row-per-lane layout.  Lane l
+// holds row rowof(l) of the tile: lanes 0-15 and 32-47 hold rows 0-15 in
+// order, lanes 16-31 and 48-63 in reverse order, so that after the LU the
+// second half of each 32-lane group can invert the reversed upper factor with
+// the same instructions that the first half uses for the lower one.  Rows
+// pass between lanes through `bc`, 64 elements of LDS that only this
+// wavefront uses: a wavefront's LDS operations execute in order, so the
+// reads of a step see its writes, and the next step's writes follow them.
+__device__ __forceinline__ int rowof(int l) { return (l & 16) ? 15 - (l & 15) : (l & 15); }
+
+// LU without interchanges of the tile held by rows (a[]: in A, out L\U).
+// Step t passes the pivot and the rest of row t from lane t to every lane.
+// Pivots of rows at or beyond `mrem` (padding, identity) are never boosted;
+// `nb` counts the boosted ones.
 template <typename T>
-__device__ __forceinline__ void lu_inv16(typename Mf<T>::v4& a, typename Mf<T>::v4& xl, typename Mf<T>::v4& xu,
-                                         T boost, int row0, int mrem, PivStats<T>& st) {
-  using M = Mf<T>;
-  const int lane = opaque(threadIdx.x & 63), cl = lane & 15, g = lane >> 4, gbase = lane & 48;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = M::row(lane, q);
-    xl[q] = (r == cl) ? T(1) : T(0);
-    xu[q] = (r == cl) ? T(1) : T(0);
-  }
+__device__ __forceinline__ void lu16_rows(T (&a)[16], T boost, int mrem, T* bc, int& nb) {
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
-    const int tg = M::grp(t), tq = M::reg(t);
-    T urow = __shfl(a[tq], tg * 16 + cl);   // U(t, cl): row t is final
-    const T xlt = __shfl(xl[tq], tg * 16 + cl);   // row t of L^{-1} is final
-    T piv = lane_read(a[tq], tg * 16 + t);
-    if (t < mrem) {
-      if (boost > T(0) && fabs(piv) < boost) {
-        piv = piv >= T(0) ? piv + boost : piv - boost;
-        st.boosts++;
-      }
-      st.minpiv = fmin(st.minpiv, (T)fabs(piv));
-      if (piv == T(0) && st.first_zero < 0) st.first_zero = row0 + t;
+    // lane indices are taken afresh each step, so that the compiler does not
+    // keep the comparisons of all steps alive at once
+    const int ln = opaque(threadIdx.x & 63), r = rowof(ln);
+    if (ln == t) {
+#pragma unroll
+      for (int c = t; c < 16; ++c) bc[c] = a[c];
     }
-    if (cl == t) urow = piv;
-    if (g == tg && cl == t) a[tq] = piv;
+    wave_lds_sync();
+    T piv = bc[t];
+    T u[16];
+#pragma unroll
+    for (int c = t + 1; c < 16; ++c) u[c] = bc[c];        // U(t, c)
+    wave_lds_sync();
+    const bool bst = boost > T(0) && t < mrem && fabs(piv) < boost;
+    piv = bst ? (piv >= T(0) ? piv + boost : piv - boost) : piv;
+    nb = opaque(nb + (bst ? 1 : 0));   // counted here, not kept as one flag per step
     const T rp = piv != T(0) ? T(1) / piv : T(0);
-    if (cl == t) {
+    // rows above t keep their values: their multiplier is zero
+    const T l = (r > t) ? a[t] * rp : T(0);
+    a[t] = (r > t) ? l : (r == t ? piv : a[t]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xu[q] *= rp;   // column t of U^{-1}
-    }
+    for (int c = t + 1; c < 16; ++c) a[c] -= l * u[c];
+  }
+}
+
+// Inverse of a unit lower triangular 16 x 16 matrix held by rows (m[c] for
+// c < the lane's row r; the diagonal is implicit), into x[] by rows, by
+// forward substitution: at step t row t of the inverse is final and passes
+// from its lane to the lanes of its 16-lane half, whose rows r > t subtract
+// m[t] times it.  Each half of a 32-lane group inverts its own matrix.
+template <typename T>
+__device__ __forceinline__ void unit_lower_inv16_rows(const T (&m)[16], T (&x)[16], T* bc) {
+  const int r0 = opaque(threadIdx.x & 15);   // not hoisted out of the caller's loop
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = M::row(lane, q);
-      const T lt = __shfl(a[q], gbase + t);     // A(r, t)
-      const T xut = __shfl(xu[q], gbase + t);   // U^{-1}(r, t)
-      if (r > t) {
-        const T l = lt * rp;
-        if (cl == t) a[q] = l;
-        else if (cl > t) a[q] -= l * urow;
-        xl[q] -= l * xlt;
-      }
-      if (cl > t) xu[q] -= xut * urow;
+  for (int c = 0; c < 16; ++c) x[c] = (c == r0) ? T(1) : T(0);
+#pragma unroll
+  for (int t = 0; t < 15; ++t) {
+    const int ln = opaque(threadIdx.x & 63), r = ln & 15;
+    T* b = bc + (ln & 16) * 2;   // this half's rows
+    if (r == t && ln < 32) {
+#pragma unroll
+      for (int c = 0; c < t; ++c) b[c] = x[c];
     }
+    wave_lds_sync();
+    T y[16];
+#pragma unroll
+    for (int c = 0; c < t; ++c) y[c] = b[c];
+    wave_lds_sync();
+    const T f = (r > t) ? m[t] : T(0);
+#pragma unroll
+    for (int c = 0; c < t; ++c) x[c] -= f * y[c];
+    x[t] -= f;
   }
 }
 
@@ -119,6 +139,7 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
   const int m = L.m;
   const BandAcc<T> A = leaf_band<T>(k, L);
   T* dv = reinterpret_cast<T*>(k.dinv) + L.dinv_off;
+  int* pflag = reinterpret_cast<int*>(lds + 2 * BUF + 64);   // step whose diagonal tile is published
   const int klf = A.kl, kuf = A.kuw;
   const int64_t s = L.start;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
@@ -208,76 +229,187 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
     st.first_zero = -1;
     double nmax = 0.0;
 
-    // panel of step jp: the caller owns column jp, acc[i] = tile (jp + i, jp)
-    // after the updates of steps < jp
-    auto panel = [&](int jp, T* Pn, v4 (&acc)[HT + 1], double cs) __attribute__((always_inline)) {
-      double t = cs;
-      t += __shfl_xor(t, 16);
-      t += __shfl_xor(t, 32);
-#pragma unroll
-      for (int off = 8; off > 0; off >>= 1) t = fmax(t, __shfl_xor(t, off));
-      nmax = fmax(nmax, t);
-      // the diagonal tile's update chain was issued first: its LU runs on
-      // the VALU while the other tiles' MFMAs are still in flight, and the
-      // raw tiles are published after it
-      v4 xl, xu;
-      lu_inv16<T>(acc[0], xl, xu, boost, 16 * jp, m - 16 * jp, st);
-      lds_put(Pn, xl);
-      lds_put(Pn + TS, xu);
-#pragma unroll
-      for (int i = 1; i <= HT; ++i) lds_put(Pn + (1 + i) * TS, acc[i]);
-      store_band(jp, jp, acc[0]);
-      T* D = dv + (int64_t)jp * dinv_stride();
-      const int ln = opaque(lane);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = M::row(ln, q);
-        D[r * 16 + (ln & 15)] = xl[q];
-        D[256 + r * 16 + (ln & 15)] = xu[q];
-      }
-    };
-
     int C = wave;
     v4 acc[HT + 1];
     double cs = 0.0;
-    if (C < nbk) {
-      load_column(C > HT ? C - HT : 0, C, acc, cs);   // rows of its first window step
-    } else {
+    // column sums of the owner's column C, gathered over its lanes into the
+    // running maximum (the 1-norm of the partition)
+    auto note_colsum = [&]() __attribute__((always_inline)) {
+      double cmax = cs;
+      cmax += __shfl_xor(cmax, 16);
+      cmax += __shfl_xor(cmax, 32);
 #pragma unroll
-      for (int i = 0; i <= HT; ++i) acc[i] = v4{T(0), T(0), T(0), T(0)};
+      for (int off = 8; off > 0; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
+      nmax = fmax(nmax, cmax);
+    };
+    // acc holds nothing that is used before it is loaded again: an empty
+    // definition tells the compiler so, which keeps the tiles out of the
+    // registers the panel needs
+    auto drop_tiles = [&]() __attribute__((always_inline)) {
+#pragma unroll
+      for (int i = 0; i <= HT; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          T x;
+          asm volatile("" : "=v"(x));
+          acc[i][q] = x;
+        }
+      }
+    };
+    // LU of diagonal tile jp (published in the U^{-1} slot of its buffer Pn)
+    // and the inverses of its factors, by the wavefront that holds no tiles
+    // in this step
+    auto panel = [&](int jp, T* Pn) __attribute__((always_inline)) {
+      // lane-derived indices are recomputed here rather than kept from
+      // outside the step loop
+      const int ln = opaque(lane), r = rowof(ln), lr = ln & 15;
+      T ar[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) ar[c] = Pn[TS + r * PADW + c];
+      wave_lds_sync();
+      T* bc = lds + 2 * BUF;
+      int nb = 0;
+      lu16_rows<T>(ar, boost, m - 16 * jp, bc, nb);
+      st.boosts += nb;
+      // this lane's pivot, and the statistics of the tile's pivots over its rows
+      T d = ar[0];
+#pragma unroll
+      for (int t = 1; t < 16; ++t) d = (r == t) ? ar[t] : d;
+      const T myrp = d != T(0) ? T(1) / d : T(0);
+      {
+        const int mrem = m - 16 * jp;
+        T mp = r < mrem ? (T)fabs(d) : T(__builtin_huge_val());
+        int fz = (r < mrem && d == T(0)) ? r : 16;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          mp = fmin(mp, __shfl_xor(mp, off));
+          fz = min(fz, __shfl_xor(fz, off));
+        }
+        st.minpiv = fmin(st.minpiv, mp);
+        if (st.first_zero < 0 && fz < 16) st.first_zero = 16 * jp + fz;
+      }
+      // L^{-1} in the first half of each 32-lane group; in the second half
+      // (L')^{-1} for L' = J V J, J the order reversal and V = D^{-1} U unit
+      // upper (row r of U times the reciprocal of its pivot), so that its
+      // row r' is row 15 - r' of V^{-1} reversed; U^{-1} = V^{-1} D^{-1}
+      const bool hi = (ln & 16) != 0;
+      T mv[16], xi[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) mv[c] = hi ? ar[15 - c] * myrp : ar[c];
+      if (ln < 32) bc[48 + r] = myrp;   // the reciprocal pivots, by row
+      unit_lower_inv16_rows<T>(mv, xi, bc);
+      T rpv[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) rpv[c] = bc[48 + c];
+      wave_lds_sync();
+      T* D = dv + (int64_t)jp * dinv_stride();
+      if (ln < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Pn[lr * PADW + c] = xi[c];
+      } else if (ln < 32) {
+        const int R = 15 - lr;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Pn[TS + R * PADW + 15 - c] = xi[c] * rpv[15 - c];   // U^{-1}(R, 15 - c)
+      }
+      if (ln < 16) {
+        const int i = 16 * jp + r;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          D[lr * 16 + c] = xi[c];
+          const int cc = 16 * jp + c;
+          if (i < m && cc < m && i - cc <= klf && cc - i <= kuf)
+            A.a[(int64_t)kuf + i - cc + (int64_t)cc * A.ldw] = ar[c];
+        }
+      } else if (ln < 32) {
+        const int R = 15 - lr;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) D[256 + R * 16 + 15 - c] = xi[c] * rpv[15 - c];
+      }
+    };
+
+    // The last wavefront's first column enters the window at step 1: it
+    // factors diagonal tile 0 (published by the owner of column 0) and loads
+    // that column in step 0; the others load theirs at once.
+    const bool first_panel = wave == NW - 1;
+    if (!first_panel) {
+      if (C < nbk) {
+        load_column(0, C, acc, cs);   // rows of its first window step
+      } else {
+#pragma unroll
+        for (int i = 0; i <= HT; ++i) acc[i] = v4{T(0), T(0), T(0), T(0)};
+      }
     }
-    if (wave == 0) panel(0, lds, acc, cs);
+    if (wave == 0) {
+      note_colsum();
+#pragma unroll
+      for (int i = 1; i <= HT; ++i) lds_put(lds + (1 + i) * TS, acc[i]);
+      lds_put(lds + TS, acc[0]);
+    }
+    if (tid == 0) *pflag = -1;
+    __syncthreads();
+    if (first_panel) {
+      panel(0, lds);
+      __builtin_amdgcn_sched_barrier(0);
+      drop_tiles();
+    }
     __syncthreads();
 
+    // Step j: the owner of column j + 1 (window column 1) updates that
+    // column first, publishes its diagonal tile and raises the flag; the
+    // wavefront that finished column j (window column 0) waits for the flag,
+    // factors the diagonal tile and publishes the inverses; the wavefront
+    // whose column enters the window next step (window column HT + 1) loads
+    // it.  One barrier ends a step; it waits for LDS operations only, so the
+    // global stores of a step stay in flight across it.
     for (int j = 0; j < nbk; ++j) {
-      const T* P = lds + (j & 1) * BUF;
       const int c = C - j;   // window column of this wavefront's tiles
+      T* Pn = lds + ((j + 1) & 1) * BUF;
       if (c == 0) {
-        // column j is final; take the column entering the window next step
+        if (j + 1 < nbk) {
+          while (__hip_atomic_load(pflag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != j + 1)
+            __builtin_amdgcn_s_sleep(1);
+          __builtin_amdgcn_s_setprio(3);
+          panel(j + 1, Pn);
+          __builtin_amdgcn_s_setprio(0);
+        }
+        // column j is final; the next column of this wavefront enters the
+        // window at step j + 2 and is loaded in step j + 1
         C += NW;
         cs = 0.0;
-        if (C < nbk) load_column(C - HT, C, acc, cs);   // window from step C - HT = j + 2 on
+        __builtin_amdgcn_sched_barrier(0);
+        drop_tiles();
+      } else if (c == HT + 1) {
+        if (C < nbk) load_column(C - HT, C, acc, cs);   // window from step j + 1 on
       } else if (c <= HT && C < nbk) {
+        const T* P = lds + (j & 1) * BUF;
         double nav[4];
         load_raw(j + 1 + HT, C, nav);   // used at the end of the step
-        const bool next_panel = (c == 1) && (j + 1 < nbk);
-        if (next_panel) __builtin_amdgcn_s_setprio(2);
+        const bool own = (c == 1) && (j + 1 < nbk);
+        if (own) __builtin_amdgcn_s_setprio(2);
         const v4 zero = {T(0), T(0), T(0), T(0)};
         const v4 u = mm_lds_reg(P, acc[0], zero);        // U_{j,C}
-        store_band(j, C, u);
         const v4 nz = -mm_lds_reg(P + TS, u, zero);      // -U_jj^{-1} U_{j,C}
-        if (j + c < nbk) store_band(j + c, j, mm_lds_lds(P + (1 + c) * TS, P + TS));   // L_{j+c,j}
+        acc[1] = mm_lds_reg(P + 2 * TS, nz, acc[1]);
+        if (own) {
+          // the next diagonal tile is final: hand it to the factoring wavefront
+          lds_put(Pn + TS, acc[1]);
+          __hip_atomic_store(pflag, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
 #pragma unroll
-        for (int i = 1; i <= HT; ++i) acc[i] = mm_lds_reg(P + (1 + i) * TS, nz, acc[i]);
+        for (int i = 2; i <= HT; ++i) acc[i] = mm_lds_reg(P + (1 + i) * TS, nz, acc[i]);
+        store_band(j, C, u);
+        if (j + c < nbk) store_band(j + c, j, mm_lds_lds(P + (1 + c) * TS, P + TS));   // L_{j+c,j}
 #pragma unroll
         for (int i = 0; i < HT; ++i) acc[i] = acc[i + 1];
         acc[HT] = make_tile(j + 1 + HT, C, nav, cs);
-        if (next_panel) {
-          panel(j + 1, lds + ((j + 1) & 1) * BUF, acc, cs);
+        if (own) {
+          note_colsum();
+#pragma unroll
+          for (int i = 1; i <= HT; ++i) lds_put(Pn + (1 + i) * TS, acc[i]);
           __builtin_amdgcn_s_setprio(0);
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
 
     if (lane == 0) {
@@ -312,10 +444,11 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
   }
 }
 
-// LDS bytes of k_flu<T, HT>: two panel buffers.
+// LDS bytes of k_flu<T, HT>: two panel buffers, the row exchange of the
+// diagonal-tile LU and the hand-over flag.
 template <typename T, int HT>
 constexpr size_t flu_lds_bytes() {
-  return (size_t)2 * (HT + 2) * 16 * tile_pad() * sizeof(T);
+  return ((size_t)2 * (HT + 2) * 16 * tile_pad() + 64) * sizeof(T) + 16;
 }
 
 template <typename T, int HT>
