@@ -43,37 +43,71 @@ struct PivStats {
   int first_zero;
 };
 
-// The diagonal tile of a panel is factored in a row-per-lane layout.  Lane l
-// holds row rowof(l) of the tile: lanes 0-15 and 32-47 hold rows 0-15 in
-// order, lanes 16-31 and 48-63 in reverse order, so that after the LU the
-// second half of each 32-lane group can invert the reversed upper factor with
-// the same instructions that the first half uses for the lower one.  Rows
-// pass between lanes through `bc`, 64 elements of LDS that only this
-// wavefront uses: a wavefront's LDS operations execute in order, so the
-// reads of a step see its writes, and the next step's writes follow them.
-__device__ __forceinline__ int rowof(int l) { return (l & 16) ? 15 - (l & 15) : (l & 15); }
+// The diagonal tile of a panel is factored in a row-per-lane layout: lane l
+// holds row l % 16 of the tile, so each 16-lane row of the wavefront holds the
+// whole tile.  Step t of an elimination passes row t from lane t to the other
+// lanes of its 16-lane row with a DPP row broadcast (a register-to-register
+// move, no LDS traffic and no wait on other wavefronts' LDS requests).
+
+// Value of lane t of this lane's 16-lane row (t a constant after unrolling).
+template <typename T>
+__device__ __forceinline__ T row_bcast(T v, int t) {
+  auto b32 = [&](int x) __attribute__((always_inline)) -> int {
+    switch (t) {
+      case 0: return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xf, 0xf, false);
+      case 1: return __builtin_amdgcn_update_dpp(0, x, 0x151, 0xf, 0xf, false);
+      case 2: return __builtin_amdgcn_update_dpp(0, x, 0x152, 0xf, 0xf, false);
+      case 3: return __builtin_amdgcn_update_dpp(0, x, 0x153, 0xf, 0xf, false);
+      case 4: return __builtin_amdgcn_update_dpp(0, x, 0x154, 0xf, 0xf, false);
+      case 5: return __builtin_amdgcn_update_dpp(0, x, 0x155, 0xf, 0xf, false);
+      case 6: return __builtin_amdgcn_update_dpp(0, x, 0x156, 0xf, 0xf, false);
+      case 7: return __builtin_amdgcn_update_dpp(0, x, 0x157, 0xf, 0xf, false);
+      case 8: return __builtin_amdgcn_update_dpp(0, x, 0x158, 0xf, 0xf, false);
+      case 9: return __builtin_amdgcn_update_dpp(0, x, 0x159, 0xf, 0xf, false);
+      case 10: return __builtin_amdgcn_update_dpp(0, x, 0x15a, 0xf, 0xf, false);
+      case 11: return __builtin_amdgcn_update_dpp(0, x, 0x15b, 0xf, 0xf, false);
+      case 12: return __builtin_amdgcn_update_dpp(0, x, 0x15c, 0xf, 0xf, false);
+      case 13: return __builtin_amdgcn_update_dpp(0, x, 0x15d, 0xf, 0xf, false);
+      case 14: return __builtin_amdgcn_update_dpp(0, x, 0x15e, 0xf, 0xf, false);
+      default: return __builtin_amdgcn_update_dpp(0, x, 0x15f, 0xf, 0xf, false);
+    }
+  };
+  if constexpr (sizeof(T) == 8) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = b32((int)(bits & 0xffffffffll)), hi = b32((int)(bits >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo));
+  } else {
+    return __int_as_float(b32(__float_as_int(v)));
+  }
+}
+
+// Value of lane 15 - (l % 16) of this lane's 16-lane row (row_mirror).
+template <typename T>
+__device__ __forceinline__ T row_mirror(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffll), 0x140, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), 0x140, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo));
+  } else {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xf, 0xf, false));
+  }
+}
 
 // LU without interchanges of the tile held by rows (a[]: in A, out L\U).
-// Step t passes the pivot and the rest of row t from lane t to every lane.
 // Pivots of rows at or beyond `mrem` (padding, identity) are never boosted;
 // `nb` counts the boosted ones.
 template <typename T>
-__device__ __forceinline__ void lu16_rows(T (&a)[16], T boost, int mrem, T* bc, int& nb) {
+__device__ __forceinline__ void lu16_rows(T (&a)[16], T boost, int mrem, int& nb) {
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
-    // lane indices are taken afresh each step, so that the compiler does not
+    // the lane index is taken afresh each step, so that the compiler does not
     // keep the comparisons of all steps alive at once
-    const int ln = opaque(threadIdx.x & 63), r = rowof(ln);
-    if (ln == t) {
-#pragma unroll
-      for (int c = t; c < 16; ++c) bc[c] = a[c];
-    }
-    wave_lds_sync();
-    T piv = bc[t];
+    const int r = opaque(threadIdx.x & 15);
+    T piv = row_bcast(a[t], t);
     T u[16];
 #pragma unroll
-    for (int c = t + 1; c < 16; ++c) u[c] = bc[c];        // U(t, c)
-    wave_lds_sync();
+    for (int c = t + 1; c < 16; ++c) u[c] = row_bcast(a[c], t);   // U(t, c)
     const bool bst = boost > T(0) && t < mrem && fabs(piv) < boost;
     piv = bst ? (piv >= T(0) ? piv + boost : piv - boost) : piv;
     nb = opaque(nb + (bst ? 1 : 0));   // counted here, not kept as one flag per step
@@ -89,26 +123,19 @@ __device__ __forceinline__ void lu16_rows(T (&a)[16], T boost, int mrem, T* bc, 
 // Inverse of a unit lower triangular 16 x 16 matrix held by rows (m[c] for
 // c < the lane's row r; the diagonal is implicit), into x[] by rows, by
 // forward substitution: at step t row t of the inverse is final and passes
-// from its lane to the lanes of its 16-lane half, whose rows r > t subtract
-// m[t] times it.  Each half of a 32-lane group inverts its own matrix.
+// from lane t of each 16-lane row to the others, whose rows r > t subtract
+// m[t] times it.  Each 16-lane row inverts its own matrix.
 template <typename T>
-__device__ __forceinline__ void unit_lower_inv16_rows(const T (&m)[16], T (&x)[16], T* bc) {
+__device__ __forceinline__ void unit_lower_inv16_rows(const T (&m)[16], T (&x)[16]) {
   const int r0 = opaque(threadIdx.x & 15);   // not hoisted out of the caller's loop
 #pragma unroll
   for (int c = 0; c < 16; ++c) x[c] = (c == r0) ? T(1) : T(0);
 #pragma unroll
   for (int t = 0; t < 15; ++t) {
-    const int ln = opaque(threadIdx.x & 63), r = ln & 15;
-    T* b = bc + (ln & 16) * 2;   // this half's rows
-    if (r == t && ln < 32) {
-#pragma unroll
-      for (int c = 0; c < t; ++c) b[c] = x[c];
-    }
-    wave_lds_sync();
+    const int r = opaque(threadIdx.x & 15);
     T y[16];
 #pragma unroll
-    for (int c = 0; c < t; ++c) y[c] = b[c];
-    wave_lds_sync();
+    for (int c = 0; c < t; ++c) y[c] = row_bcast(x[c], t);
     const T f = (r > t) ? m[t] : T(0);
 #pragma unroll
     for (int c = 0; c < t; ++c) x[c] -= f * y[c];
@@ -139,10 +166,21 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
   const int m = L.m;
   const BandAcc<T> A = leaf_band<T>(k, L);
   T* dv = reinterpret_cast<T*>(k.dinv) + L.dinv_off;
-  int* pflag = reinterpret_cast<int*>(lds + 2 * BUF + 64);   // step whose diagonal tile is published
+  int* pflag = reinterpret_cast<int*>(lds + 2 * BUF);   // step whose diagonal tile is published
   const int klf = A.kl, kuf = A.kuw;
   const int64_t s = L.start;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
+  // Wavefront w owns the tile columns C = role(w) (mod NW).  The wavefronts
+  // of a workgroup are normally placed on the four SIMDs of a compute unit
+  // in turn (w on SIMD w % 4; any placement gives the same results), so
+  // role(w) numbers the wavefronts of SIMD 0 first, then those of SIMD 1, and
+  // so on: wavefronts that share a SIMD hold neighbouring columns, and the
+  // factoring wavefront of a step (window column 0) often shares its SIMD
+  // with the owner of the next panel column (window column 1) or with the
+  // loading wavefront (window column NW - 1), which issue few or no
+  // matrix-core products while it factors, rather than with two wavefronts
+  // that issue a full step of them.
+  const int role = (wave % 4) * (NW / 4) + min(wave % 4, NW % 4) + wave / 4;
   constexpr int DQ = sizeof(T) == 8 ? 4 : 1;   // row step between registers
   const int nbk = (m + 15) / 16;
 
@@ -229,7 +267,7 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
     st.first_zero = -1;
     double nmax = 0.0;
 
-    int C = wave;
+    int C = role;
     v4 acc[HT + 1];
     double cs = 0.0;
     // column sums of the owner's column C, gathered over its lanes into the
@@ -262,14 +300,13 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
     auto panel = [&](int jp, T* Pn) __attribute__((always_inline)) {
       // lane-derived indices are recomputed here rather than kept from
       // outside the step loop
-      const int ln = opaque(lane), r = rowof(ln), lr = ln & 15;
+      const int ln = opaque(lane), r = ln & 15;
       T ar[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) ar[c] = Pn[TS + r * PADW + c];
       wave_lds_sync();
-      T* bc = lds + 2 * BUF;
       int nb = 0;
-      lu16_rows<T>(ar, boost, m - 16 * jp, bc, nb);
+      lu16_rows<T>(ar, boost, m - 16 * jp, nb);
       st.boosts += nb;
       // this lane's pivot, and the statistics of the tile's pivots over its rows
       T d = ar[0];
@@ -288,49 +325,51 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
         st.minpiv = fmin(st.minpiv, mp);
         if (st.first_zero < 0 && fz < 16) st.first_zero = 16 * jp + fz;
       }
-      // L^{-1} in the first half of each 32-lane group; in the second half
-      // (L')^{-1} for L' = J V J, J the order reversal and V = D^{-1} U unit
-      // upper (row r of U times the reciprocal of its pivot), so that its
-      // row r' is row 15 - r' of V^{-1} reversed; U^{-1} = V^{-1} D^{-1}
-      const bool hi = (ln & 16) != 0;
-      T mv[16], xi[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) mv[c] = hi ? ar[15 - c] * myrp : ar[c];
-      if (ln < 32) bc[48 + r] = myrp;   // the reciprocal pivots, by row
-      unit_lower_inv16_rows<T>(mv, xi, bc);
-      T rpv[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) rpv[c] = bc[48 + c];
-      wave_lds_sync();
       T* D = dv + (int64_t)jp * dinv_stride();
-      if (ln < 16) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) Pn[lr * PADW + c] = xi[c];
-      } else if (ln < 32) {
-        const int R = 15 - lr;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) Pn[TS + R * PADW + 15 - c] = xi[c] * rpv[15 - c];   // U^{-1}(R, 15 - c)
-      }
       if (ln < 16) {
         const int i = 16 * jp + r;
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          D[lr * 16 + c] = xi[c];
           const int cc = 16 * jp + c;
           if (i < m && cc < m && i - cc <= klf && cc - i <= kuf)
             A.a[(int64_t)kuf + i - cc + (int64_t)cc * A.ldw] = ar[c];
         }
-      } else if (ln < 32) {
-        const int R = 15 - lr;
+      }
+      // L^{-1} in lanes 0-15 (and 32-47); in lanes 16-31 (and 48-63)
+      // (L')^{-1} for L' = J V J, J the order reversal and V = D^{-1} U unit
+      // upper (row r of U times the reciprocal of its pivot): lane 16 + r'
+      // takes row 15 - r' of the tile reversed, so that its row of the
+      // inverse is row 15 - r' of V^{-1} reversed; U^{-1} = V^{-1} D^{-1}
+      const bool hi = (ln & 16) != 0;
+      const T rpm = row_mirror(myrp);
+      T mv[16], xi[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) D[256 + R * 16 + 15 - c] = xi[c] * rpv[15 - c];
+      for (int c = 0; c < 16; ++c) {
+        const T am = row_mirror(ar[15 - c]);
+        mv[c] = hi ? am * rpm : ar[c];
+      }
+      unit_lower_inv16_rows<T>(mv, xi);
+      if (ln < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          Pn[r * PADW + c] = xi[c];
+          D[r * 16 + c] = xi[c];
+        }
+      } else if (ln < 32) {
+        const int R = 15 - r;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const T v = xi[c] * row_bcast(myrp, 15 - c);   // U^{-1}(R, 15 - c)
+          Pn[TS + R * PADW + 15 - c] = v;
+          D[256 + R * 16 + 15 - c] = v;
+        }
       }
     };
 
     // The last wavefront's first column enters the window at step 1: it
     // factors diagonal tile 0 (published by the owner of column 0) and loads
     // that column in step 0; the others load theirs at once.
-    const bool first_panel = wave == NW - 1;
+    const bool first_panel = role == NW - 1;
     if (!first_panel) {
       if (C < nbk) {
         load_column(0, C, acc, cs);   // rows of its first window step
@@ -339,7 +378,7 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
         for (int i = 0; i <= HT; ++i) acc[i] = v4{T(0), T(0), T(0), T(0)};
       }
     }
-    if (wave == 0) {
+    if (role == 0) {
       note_colsum();
 #pragma unroll
       for (int i = 1; i <= HT; ++i) lds_put(lds + (1 + i) * TS, acc[i]);
@@ -391,10 +430,12 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
         const v4 nz = -mm_lds_reg(P + TS, u, zero);      // -U_jj^{-1} U_{j,C}
         acc[1] = mm_lds_reg(P + 2 * TS, nz, acc[1]);
         if (own) {
-          // the next diagonal tile is final: hand it to the factoring wavefront
+          // the next diagonal tile is final: hand it to the factoring
+          // wavefront before any other work of the step is issued
           lds_put(Pn + TS, acc[1]);
           __hip_atomic_store(pflag, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 2; i <= HT; ++i) acc[i] = mm_lds_reg(P + (1 + i) * TS, nz, acc[i]);
         store_band(j, C, u);
@@ -444,11 +485,10 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
   }
 }
 
-// LDS bytes of k_flu<T, HT>: two panel buffers, the row exchange of the
-// diagonal-tile LU and the hand-over flag.
+// LDS bytes of k_flu<T, HT>: two panel buffers and the hand-over flag.
 template <typename T, int HT>
 constexpr size_t flu_lds_bytes() {
-  return ((size_t)2 * (HT + 2) * 16 * tile_pad() + 64) * sizeof(T) + 16;
+  return (size_t)2 * (HT + 2) * 16 * tile_pad() * sizeof(T) + 16;
 }
 
 template <typename T, int HT>
