@@ -148,6 +148,23 @@ inline V mfma16x16x4(S a, S bb, V c, bool f64) {
   return d;
 }
 
+// __builtin_amdgcn_update_dpp for the row controls the kernels replayed here
+// use: row_newbcast:n (0x150 + n, lane n of each 16-lane row to the whole
+// row) and row_mirror (0x140, lane 15 - i of each row to lane i).
+inline int update_dpp(int v, int ctrl) {
+  Block* b = cur_block();
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  b->slot[w][l] = (uint64_t)(uint32_t)v;
+  b->wave[w].arrive();
+  int src;
+  if (ctrl >= 0x150 && ctrl <= 0x15f) src = (l & 48) + (ctrl - 0x150);
+  else if (ctrl == 0x140) src = (l & 48) + 15 - (l & 15);
+  else std::abort();
+  const int r = (int)(uint32_t)b->slot[w][src];
+  b->wave[w].arrive();
+  return r;
+}
+
 struct Pair2 {
   unsigned v[2];
   unsigned operator[](int i) const { return v[i]; }
@@ -161,7 +178,7 @@ struct Pair2 {
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) ::emu::mfma16x16x4<float>((a), (b), (c), false)
 #define __builtin_amdgcn_permlane16_swap(...) ::emu::unsupported_pair()
 #define __builtin_amdgcn_permlane32_swap(...) ::emu::unsupported_pair()
-#define __builtin_amdgcn_update_dpp(...) ::emu::unsupported_int()
+#define __builtin_amdgcn_update_dpp(old, v, ctrl, rm, bm, bc) ::emu::update_dpp((v), (ctrl))
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 #define __builtin_amdgcn_fence(...) ((void)0)
 

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1811_03559_amd", "csrc")
 HEADERS = ["spike_device.hpp", "spike_kernels.hpp", "spike_tile.hpp", "spike_launch.hpp", "spike_profile.hpp",
-           "spike_types.hpp", "spike_plan.hpp", "spike_plan.cpp"]
+           "spike_types.hpp", "spike_plan.hpp", "spike_plan.cpp", "spike_rowlu.hpp"]
 
 
 def _rewrite(text: str) -> str:
@@ -34,9 +34,8 @@ def _rewrite(text: str) -> str:
     return text
 
 
-def build(workdir: str | None = None) -> str:
-    """Compile the replay; returns the executable's path."""
-    work = workdir or tempfile.mkdtemp(prefix="spike_hostemu_")
+def _sources(work: str) -> str:
+    """The rewritten kernel headers under work/p/csrc; returns that folder."""
     src = os.path.join(work, "p", "csrc")
     os.makedirs(src, exist_ok=True)
     os.makedirs(os.path.join(work, "include"), exist_ok=True)
@@ -46,13 +45,51 @@ def build(workdir: str | None = None) -> str:
             t = f.read()
         with open(os.path.join(src, h), "w") as f:
             f.write(_rewrite(t))
-    exe = os.path.join(work, "emu_main")
+    return src
+
+
+def _compile(work: str, main: str, extra: list[str], name: str) -> str:
+    src = _sources(work)
+    exe = os.path.join(work, name)
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-pthread",
-           "-I", HERE, "-I", src, os.path.join(HERE, "emu_main.cpp"), os.path.join(src, "spike_plan.cpp"),
-           "-o", exe]
+           "-I", HERE, "-I", src, os.path.join(HERE, main), os.path.join(HERE, "emu_runtime.cpp"),
+           *[os.path.join(src, e) for e in extra], "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return exe
+
+
+def build(workdir: str | None = None) -> str:
+    """Compile the replay; returns the executable's path."""
+    work = workdir or tempfile.mkdtemp(prefix="spike_hostemu_")
+    return _compile(work, "emu_main.cpp", ["spike_plan.cpp"], "emu_main")
+
+
+def build_tile_lu(workdir: str | None = None) -> str:
+    """Compile the replay of the diagonal-tile LU of the block LU (the
+    row-per-lane routines of spike_rowlu.hpp, one wavefront); returns the
+    executable's path."""
+    work = workdir or tempfile.mkdtemp(prefix="spike_hostemu_lu_")
+    return _compile(work, "tile_lu_main.cpp", [], "tile_lu_main")
+
+
+def run_tile_lu(exe: str, tiles: np.ndarray, boost: float, mrem: int, fp32: bool = False):
+    """Factor each 16 x 16 tile of `tiles` (count x 16 x 16) as the block LU's
+    panel does: returns (L\\U, L^{-1}, U^{-1}, boosted pivot counts), the
+    matrices row-major like the tiles."""
+    tiles = np.ascontiguousarray(tiles, dtype=np.float64).reshape(-1, 16, 16)
+    work = tempfile.mkdtemp(prefix="spike_hostemu_lu_run_")
+    fin, fout = os.path.join(work, "in.bin"), os.path.join(work, "out.bin")
+    with open(fin, "wb") as f:
+        np.array([tiles.shape[0], mrem, int(fp32)], dtype=np.int64).tofile(f)
+        np.array([boost], dtype=np.float64).tofile(f)
+        tiles.tofile(f)
+    subprocess.run([exe, fin, fout], check=True, capture_output=True, text=True, timeout=300)
+    cnt = tiles.shape[0]
+    raw = np.fromfile(fout, dtype=np.float64, count=cnt * 768).reshape(cnt, 3, 16, 16)
+    nb = np.fromfile(fout, dtype=np.int64, offset=cnt * 768 * 8, count=cnt)
+    shutil.rmtree(work, ignore_errors=True)
+    return raw[:, 0], raw[:, 1], raw[:, 2], nb
 
 
 def run(exe: str, ab: np.ndarray, kl: int, ku: int, F: np.ndarray, p: int, pivot: bool, trans: bool,

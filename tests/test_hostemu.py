@@ -126,3 +126,97 @@ def test_paper_tree_ratio_sizing(exe, pivot, trans):
     _check(ab, k, k, F, X, trans)
     sweep_table.check(sweep_table.from_array(sw), p,
                       stages=("factor", "solve_t" if trans else "solve"))
+
+
+# ---- the diagonal-tile LU of the block LU (row-per-lane, DPP row broadcasts)
+
+@pytest.fixture(scope="module")
+def tile_exe(tmp_path_factory):
+    return replay.build_tile_lu(str(tmp_path_factory.mktemp("hostemu_lu")))
+
+
+def _plain_lu(A, boost, mrem):
+    """LU without interchanges, written out step by step: at step t the pivot
+    A(t, t) (raised by `boost` in magnitude when below it, for t < mrem), the
+    multipliers below it and the rank-1 update of the trailing block."""
+    a = np.array(A, dtype=np.float64)
+    nb = 0
+    for t in range(16):
+        piv = a[t, t]
+        if boost > 0 and t < mrem and abs(piv) < boost:
+            piv = piv + boost if piv >= 0 else piv - boost
+            nb += 1
+        a[t, t] = piv
+        for r in range(t + 1, 16):
+            a[r, t] = a[r, t] / piv
+            a[r, t + 1:] -= a[r, t] * a[t, t + 1:]
+    return a, nb
+
+
+def _tiles(rng, count, dominant):
+    A = rng.standard_normal((count, 16, 16))
+    if dominant:
+        A += np.eye(16) * rng.uniform(4.0, 8.0, (count, 1, 1))
+    return A
+
+
+@pytest.mark.parametrize("dominant", [True, False])
+def test_tile_lu_factors_and_inverses(tile_exe, dominant):
+    rng = np.random.default_rng(11 + dominant)
+    A = _tiles(rng, 12, dominant)
+    lu, li, ui, nb = replay.run_tile_lu(tile_exe, A, 0.0, 16)
+    assert (nb == 0).all()
+    for i in range(len(A)):
+        ref, _ = _plain_lu(A[i], 0.0, 16)
+        L = np.tril(lu[i], -1) + np.eye(16)
+        U = np.triu(lu[i])
+        grow = max(1.0, np.abs(ref).max())
+        assert np.abs(lu[i] - ref).max() <= 1e-12 * grow
+        assert np.abs(L @ U - A[i]).max() <= 1e-13 * np.abs(A[i]).max() * grow
+        # the inverses, against the identity
+        assert np.abs(li[i] @ L - np.eye(16)).max() <= 1e-12 * max(1.0, np.abs(li[i]).max())
+        assert np.abs(ui[i] @ U - np.eye(16)).max() <= 1e-12 * max(1.0, np.abs(ui[i]).max() * np.abs(U).max())
+        assert np.allclose(np.triu(li[i], 1), 0.0) and np.allclose(np.tril(ui[i], -1), 0.0)
+        assert np.allclose(np.diag(li[i]), 1.0)
+
+
+def test_tile_lu_boosting_and_padding(tile_exe):
+    rng = np.random.default_rng(5)
+    A = _tiles(rng, 10, False) * 0.3
+    boost = 0.5
+    for mrem in (16, 9, 1):
+        B = A.copy()
+        if mrem < 16:   # rows and columns past the order are the identity
+            B[:, mrem:, :] = 0.0
+            B[:, :, mrem:] = 0.0
+            B[:, mrem:, mrem:] = np.eye(16 - mrem)
+        lu, li, ui, nb = replay.run_tile_lu(tile_exe, B, boost, mrem)
+        for i in range(len(B)):
+            ref, rnb = _plain_lu(B[i], boost, mrem)
+            assert nb[i] == rnb
+            assert np.abs(lu[i] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+            piv = np.diag(lu[i])[:mrem]
+            assert (np.abs(piv) >= boost * (1 - 1e-15)).all()
+            U = np.triu(lu[i])
+            assert np.abs(ui[i] @ U - np.eye(16)).max() <= 1e-11 * max(1.0, np.abs(ui[i]).max() * np.abs(U).max())
+
+
+def test_tile_lu_zero_pivot_stays_finite(tile_exe):
+    A = np.eye(16)[None].copy()
+    A[0, 5, 5] = 0.0
+    lu, li, ui, nb = replay.run_tile_lu(tile_exe, A, 0.0, 16)
+    assert lu[0, 5, 5] == 0.0
+    assert np.isfinite(lu).all() and np.isfinite(li).all() and np.isfinite(ui).all()
+    assert (ui[0, 5] == 0.0).all()   # the reciprocal of a zero pivot is taken as zero
+
+
+def test_tile_lu_single_precision(tile_exe):
+    rng = np.random.default_rng(21)
+    A = _tiles(rng, 6, True).astype(np.float32).astype(np.float64)
+    lu, li, ui, nb = replay.run_tile_lu(tile_exe, A, 0.0, 16, fp32=True)
+    for i in range(len(A)):
+        L = np.tril(lu[i], -1) + np.eye(16)
+        U = np.triu(lu[i])
+        assert np.abs(L @ U - A[i]).max() <= 2e-6 * np.abs(A[i]).max()
+        assert np.abs(li[i] @ L - np.eye(16)).max() <= 2e-6
+        assert np.abs(ui[i] @ U - np.eye(16)).max() <= 2e-6
