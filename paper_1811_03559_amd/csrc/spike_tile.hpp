@@ -351,19 +351,26 @@ __device__ void tile_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
       for (int i = 0; i < 4; ++i) dst.store(16 * j + M::row(lane, i), col, (double)xv[i]);
     }
     if (wave_active) {
+      // the product of pending block s lands in slot s - 1 (the window
+      // moves down one block per step): the last product of each chain
+      // writes the register of the slot it moves to, so the window shifts
+      // without register moves
+      v4 t[HT + 1];
+#pragma unroll
+      for (int s = 1; s <= HT; ++s) t[s] = acc[s];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int s = 1; s <= HT; ++s)
-          acc[s] = M::mma(-sld(P + (s * 16 + (lane & 15)) * PADW + M::row(lane, i)), xv[i], acc[s]);
+          t[s] = M::mma(-sld(P + (s * 16 + (lane & 15)) * PADW + M::row(lane, i)), xv[i], t[s]);
       }
+#pragma unroll
+      for (int s = 1; s <= HT; ++s) acc[s - 1] = t[s];
     }
     // 3. next panel into the other buffer
     if (more) store_panel(lds + (b ^ 1) * PAN, pf);
     __syncthreads();
-#pragma unroll
-    for (int s = 0; s < HT; ++s) acc[s] = acc[s + 1];
-    acc[HT] = nxt;
+    acc[HT] = nxt;   // (a wavefront without columns keeps zeros or stale tiles it never stores)
   }
 }
 
