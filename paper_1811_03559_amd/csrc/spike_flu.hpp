@@ -213,7 +213,7 @@ __device__ __forceinline__ void flu_body(const KParams& k, const LeafDesc& L, T*
       T d = ar[0];
 #pragma unroll
       for (int t = 1; t < 16; ++t) d = (r == t) ? ar[t] : d;
-      const T myrp = d != T(0) ? T(1) / d : T(0);
+      const T myrp = d != T(0) ? recip(d) : T(0);
       {
         const int mrem = m - 16 * jp;
         T mp = r < mrem ? (T)fabs(d) : T(__builtin_huge_val());

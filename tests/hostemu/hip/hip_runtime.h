@@ -180,6 +180,8 @@ struct Pair2 {
 #define __builtin_amdgcn_permlane32_swap(...) ::emu::unsupported_pair()
 #define __builtin_amdgcn_update_dpp(old, v, ctrl, rm, bm, bc) ::emu::update_dpp((v), (ctrl))
 #define __builtin_amdgcn_wave_barrier() ((void)0)
+#define __builtin_amdgcn_rcp(x) (1.0 / (double)(x))
+#define __builtin_amdgcn_rcpf(x) (1.0f / (float)(x))
 #define __builtin_amdgcn_fence(...) ((void)0)
 
 template <typename A, typename B> inline auto min(A a, B b) -> decltype(a < b ? a : b) { return a < b ? a : b; }

@@ -25,7 +25,7 @@ static void factor_tile(const double* in, double boost, int mrem, double* out, l
     lu16_rows<T>(ar, (T)boost, mrem, nb);
     T d = ar[0];
     for (int t = 1; t < 16; ++t) d = (r == t) ? ar[t] : d;
-    const T myrp = d != T(0) ? T(1) / d : T(0);
+    const T myrp = d != T(0) ? recip(d) : T(0);
     if (ln < 16)
       for (int c = 0; c < 16; ++c) out[r * 16 + c] = (double)ar[c];
     const bool hi = (ln & 16) != 0;
