@@ -17,6 +17,7 @@
 #pragma once
 #include "spike_gemv.hpp"
 #include "spike_kernels.hpp"
+#include "spike_rowlu.hpp"
 
 namespace spike {
 
@@ -752,7 +753,7 @@ __device__ __forceinline__ void mlu_blk_body(const KParams& k, const int bx_, co
             rstep[p] = s0 + t;
             pvt[bb * 16 + t] = p;
           }
-          const double rp = piv != 0.0 ? 1.0 / piv : 0.0;
+          const double rp = piv != 0.0 ? recip(piv) : 0.0;
           double l[RS];
 #pragma unroll
           for (int s = 0; s < RS; ++s) {
