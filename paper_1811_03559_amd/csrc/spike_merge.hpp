@@ -759,7 +759,10 @@ __device__ __forceinline__ void mlu_blk_body(const KParams& k, const int bx_, co
           for (int s = 0; s < RS; ++s) {
             const bool open = !(rch & (1u << s));
             l[s] = open ? pr[s][t] * rp : 0.0;
-            if (open) pr[s][t] = l[s];
+            pr[s][t] = open ? l[s] : pr[s][t];
+            // settled here: otherwise the compiler keeps every step's
+            // multipliers and old column values alive to the end of the block
+            asm volatile("" : "+v"(pr[s][t]));
           }
 #pragma unroll
           for (int c = t + 1; c < 16; ++c) {
