@@ -360,9 +360,10 @@ __device__ void tile_sweep(const Acc& A, const T* dinv, const TSrc& src, const T
       for (int s = 1; s <= HT; ++s) t[s] = acc[s];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        const T nx = -xv[i];   // (-a) b = a (-b) exactly: one negation per step, not one per product
 #pragma unroll
         for (int s = 1; s <= HT; ++s)
-          t[s] = M::mma(-sld(P + (s * 16 + (lane & 15)) * PADW + M::row(lane, i)), xv[i], t[s]);
+          t[s] = M::mma(sld(P + (s * 16 + (lane & 15)) * PADW + M::row(lane, i)), nx, t[s]);
       }
 #pragma unroll
       for (int s = 1; s <= HT; ++s) acc[s - 1] = t[s];
