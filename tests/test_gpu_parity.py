@@ -168,6 +168,25 @@ def test_zero_pivot_boosting_and_pivoting():
     check(ab, k, k, F, X, pivot=True)
 
 
+@pytest.mark.parametrize("k", [160, 128])
+@pytest.mark.parametrize("last", [False, True])
+def test_zero_pivot_boosting_wide_band(k, last):
+    """The same at the block LU's widest windows (k = 160: 10 tiles, k = 128:
+    8), where the boosted second pass reruns the panel hand-over: the zero
+    pivot opens a middle partition, or the last partition, which is factored
+    as the LU of its reversal (its first pivot is its last row)."""
+    n, p = 4 * 1200, 4
+    ab = dd_band(n, k, k, 17 + k)
+    s = n - 1 if last else 1200   # first pivot of the partition's factorisation
+    ab[s, k] = 0.0
+    F = inputs.rhs(n, 1, inputs.rng_for(18 + k))
+    _, info, _ = run(ab, k, k, F, p=p, pivot=False, boost_tau=0.0)
+    assert info["info"] == s + 1
+    X, info, _ = run(ab, k, k, F, p=p, pivot=False, max_refine=10)
+    assert info["n_boosts"] >= 1 and info["info"] == 0
+    check(ab, k, k, F, X, pivot=True)
+
+
 @pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("pivot", [False, True])
 def test_mixed_precision_refinement(trans, pivot):
