@@ -263,13 +263,13 @@ def test_workspace_prefilled_with_nan(precision, trans, pivot):
     check(ab, k, k, F, X, trans=trans, pivot=pivot, X_true=X_true)
 
 
-@pytest.mark.parametrize("k", [48, 64, 128])
+@pytest.mark.parametrize("k", [48, 64, 128, 160])
 @pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_single_rhs_window_heights(k, trans, precision):
     """nrhs = 1 (the single-right-hand-side sweep engine the benchmark's solve
-    runs) at the window heights of k = 48, 64 (4 tiles of 16 rows) and 128
-    (8 tiles), FP64 (cfg1 recipe, diagonal = row abs-sum x 1.05) and FP32
+    runs) at the window heights of k = 48, 64 (4 tiles of 16 rows), 128
+    (8 tiles) and 160 (10 tiles, the benchmark's), FP64 (cfg1 recipe, diagonal = row abs-sum x 1.05) and FP32
     factors with FP64 refinement (cfg3 recipe), against the oracle over
     partitions of several tiles with ragged sizes."""
     p = 6
